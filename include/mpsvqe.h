@@ -1,0 +1,180 @@
+/*
+ * mpsvqe.h -- C ABI of the MI355X (gfx950) differentiable-MPS VQE engine.
+ *
+ * The engine simulates a variational circuit on a matrix product state and
+ * returns the energy of a qubit Hamiltonian and its gradient, following
+ * arXiv:2211.07983:
+ *   - the Hartree-Fock product state as a D=1 MPS (Sec. 3, Eq. hf);
+ *   - nearest-neighbour two-qubit gates applied with the Hastings update that
+ *     keeps the right-canonical form and the Schmidt values (Sec. 3, Eq.
+ *     rightcanonicalcondition and the two-qubit gate passage), truncated to at
+ *     most D Schmidt values above a threshold eps;
+ *   - E = sum_k c_k <psi|P_k|psi> as one-dimensional network contractions
+ *     (Sec. 2, Eq. expect-val; Sec. 3, Eq. paulistringexp);
+ *   - dE/dtheta by reverse mode through every gate, SVD and sweep (the local
+ *     gradient discussed in Sec. 4, with the complex rules of App. A, Eqs.
+ *     bp1-bp4), checkpointed and recomputed in the backward pass.
+ *
+ * Conventions (all calls):
+ *   - Qubit q is MPS site q; q = 0 is the leftmost ket bit; |1> = occupied.
+ *   - Bond k sits between sites k and k+1 (0 <= k <= n_qubits-2).
+ *   - A 4x4 gate acting on bond k has row index 2*i'_k + i'_{k+1} and column
+ *     index 2*i_k + i_{k+1}; complex numbers are (re, im) double pairs.
+ *   - A Pauli string is a pair of bit masks (x, z), bit q%64 of word q/64 for
+ *     qubit q; per qubit I=(0,0), X=(1,0), Z=(0,1), Y=(1,1); the operator is
+ *     i^{|x&z|} X^x Z^z.
+ *   - RZZ(phi) = exp(-i phi/2 Z(x)Z) = diag(e^{-i phi/2}, e^{i phi/2},
+ *     e^{i phi/2}, e^{-i phi/2}).
+ *
+ * Ownership: input arrays are read during the call only; states and plans
+ * copy what they keep (to device memory).  Objects returned through an out
+ * pointer belong to the caller and are released with the matching *_free.
+ *
+ * Errors: every call returns an mps_status; no exception crosses the ABI.  On
+ * error the outputs are not written and mps_last_error() describes it.  A
+ * context is bound to one device and one HIP stream; it is not thread safe
+ * (use one context per host thread).  Host pointers are plain host memory
+ * unless a flag says a pointer is a device address.
+ */
+#ifndef MPSVQE_H
+#define MPSVQE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mps_status;
+enum {
+  MPS_OK = 0,
+  MPS_EINVAL = -1,   /* invalid argument (sizes, indices, NaN/Inf)           */
+  MPS_ENOMEM = -2,   /* device allocation failed or capacity exceeded        */
+  MPS_EDEVICE = -3,  /* HIP runtime error                                   */
+  MPS_ENOCONV = -4,  /* Jacobi SVD did not converge within max_sweeps       */
+  MPS_EDEGEN = -5    /* degenerate singular pair carries a cotangent        */
+};
+
+typedef struct mps_ctx mps_ctx;
+typedef struct mps_state mps_state;
+typedef struct mps_plan mps_plan;
+
+/* Truncation of every two-qubit update (Sec. 3): keep
+ * r = min(d_max, #{s_i > eps}) >= 1 Schmidt values of the normalised state
+ * and renormalise them.  precision: 0 = FP64 everywhere.                     */
+typedef struct {
+  int32_t d_max;
+  double eps;
+  int32_t precision;
+} mps_trunc;
+
+/* A compiled nearest-neighbour circuit (Sec. 3, two-qubit gates; Sec. 2,
+ * UCCSD as Pauli rotations).  Gate g acts on bond bond[g]:
+ *   kind[g] == 0 (FIXED): Q = pre[g]
+ *   kind[g] == 1 (PARAM): Q = post[g] . RZZ(coeff[g] * theta[param[g]]) . pre[g]
+ * pre/post: [n_gates][4][4][2] doubles (row-major 4x4, then re/im).          */
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_gates;
+  const int32_t* bond;
+  const int32_t* kind;
+  const double* pre;
+  const double* post;
+  const int32_t* param;
+  const double* coeff;
+} mps_circuit;
+
+/* H = c0 + sum_k coeff[k] P_k (Sec. 2, Eq. expect-val); x_mask/z_mask are
+ * [n_terms][words] with words = ceil(n_qubits/64); coeff is real.           */
+typedef struct {
+  int32_t n_qubits;
+  int64_t n_terms;
+  int32_t words;
+  const uint64_t* x_mask;
+  const uint64_t* z_mask;
+  const double* coeff;
+  double c0;
+} mps_paulisum;
+
+/* Backward-pass options: ckpt_gates = gates per checkpoint segment (the MPS
+ * is saved every ckpt_gates gates and each segment is recomputed in reverse);
+ * broaden = eta of the Lorentzian 1/(s_j^2-s_i^2) -> d/(d^2+eta^2) (0 = off);
+ * max_sweeps = Jacobi sweep limit; strict_degenerate = 1 makes a degenerate
+ * singular pair that carries a cotangent an error (MPS_EDEGEN).            */
+typedef struct {
+  int32_t ckpt_gates;
+  double broaden;
+  int32_t max_sweeps;
+  int32_t strict_degenerate;
+} mps_grad_opts;
+
+/* Per-call statistics (any pointer to it may be NULL).                     */
+typedef struct {
+  double discarded_weight_sum;  /* sum over gates of discarded s^2 / total s^2 */
+  double discarded_weight_max;
+  double norm;                  /* Z = <psi|psi> of the final stored MPS        */
+  double imag_E;                /* imaginary part of the energy sum            */
+  int32_t max_bond;
+  int32_t gates_truncated;      /* gates with discarded weight > 0            */
+  int32_t max_sweeps_used;
+  int32_t degenerate_cuts;      /* cuts with s_r - s_{r+1} < 1e-10 s_1         */
+  double t_gates_ms, t_sweep_ms, t_backward_ms;
+  int64_t n_gates_applied;
+} mps_stats;
+
+/* Context on HIP device `device` using `hip_stream` (a hipStream_t; NULL =
+ * the null stream).  Returns MPS_EDEVICE if the device is not usable.       */
+mps_status mps_ctx_create(int32_t device, void* hip_stream, mps_ctx** out);
+void mps_ctx_destroy(mps_ctx* ctx);
+/* Text of the last error on ctx; valid until the next call on ctx.          */
+const char* mps_last_error(const mps_ctx* ctx);
+
+/* Sec. 3, Eq. hf: the product state |b_0 ... b_{N-1}> as a D=1 MPS with
+ * capacity trunc->d_max on every bond.  occ_bits: host [n_qubits], 0 or 1.  */
+mps_status mps_init_product(mps_ctx* ctx, int32_t n_qubits, const uint8_t* occ_bits,
+                            const mps_trunc* trunc, mps_state** out);
+
+/* Sec. 3 / Sec. 4 Eq. circuitevolve: apply every gate of `circuit` in order
+ * with the Hastings update and truncation.  theta: host [n_theta].  On
+ * validation failure the state is unchanged.                               */
+mps_status mps_apply_circuit(mps_state* st, const mps_circuit* circuit, const double* theta,
+                             int32_t n_theta, mps_stats* stats);
+
+/* Sec. 2 Eq. expect-val / Sec. 3 Eq. paulistringexp: energy = c0 +
+ * sum_k coeff[k] <P_k> / <psi|psi> with a compensated final sum.
+ * term_vals (nullable): host [n_terms] normalised <P_k> (real part).         */
+mps_status mps_expect_paulisum(mps_state* st, const mps_paulisum* h, double* energy,
+                               double* term_vals, mps_stats* stats);
+
+/* A reusable device copy of (initial state, circuit, Hamiltonian, options). */
+mps_status mps_plan_create(mps_ctx* ctx, const uint8_t* occ_bits, const mps_circuit* circuit,
+                           const mps_paulisum* h, const mps_trunc* trunc,
+                           const mps_grad_opts* opts, mps_plan** out);
+
+/* Sec. 4 (Eqs. expec, expecgrad, circuitevolvegrad): energy and
+ * grad[p] = dE/dtheta_p.  theta and grad are host arrays, or device
+ * addresses (on the context's device) when theta_on_device != 0; a device
+ * theta must stay valid until the call returns.                            */
+mps_status mps_energy_grad(mps_plan* plan, const double* theta, int32_t n_theta,
+                           int32_t theta_on_device, double* energy, double* grad,
+                           mps_stats* stats);
+
+/* Forward pass of a plan only (energy at theta, no gradient).              */
+mps_status mps_plan_energy(mps_plan* plan, const double* theta, int32_t n_theta,
+                           double* energy, mps_stats* stats);
+
+/* Test access: bond dimensions (host int32 [n_qubits+1], dims[k] = bond left
+ * of site k), site tensors and Schmidt vectors.  B: host complex [n][dl][2][dr]
+ * packed per site in site order; lam: host double [n_qubits+1][d_max].      */
+mps_status mps_state_export(const mps_state* st, int32_t* dims, double* B, double* lam);
+int64_t mps_state_size(const mps_state* st);   /* doubles needed by B above */
+int32_t mps_state_qubits(const mps_state* st);
+
+void mps_state_free(mps_state* st);
+void mps_plan_free(mps_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPSVQE_H */

@@ -1,0 +1,108 @@
+// Host-side objects behind the opaque ABI handles.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/mpsvqe.h"
+#include "engine.h"
+
+// Owning device allocation that grows on demand.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  void release();
+  void* ensure(size_t n);
+};
+
+struct DevCircuit {
+  int G = 0;
+  GateTable tab{};
+  std::vector<int> bond_h, kind_h, param_h;
+  std::vector<double> coeff_h;
+  DevBuf d_bond, d_kind, d_pre, d_post, d_param, d_coeff;
+  void upload_from(const mps_circuit* c, hipStream_t s);
+};
+
+struct SiteList {
+  size_t job_off = 0, fin_off = 0;
+  int njobs = 0, nfin = 0;
+};
+
+struct Chunk {
+  int lo = 0, hi = -1;
+  std::vector<SiteList> sites;
+};
+
+struct DevHamiltonian {
+  int64_t K = 0;
+  double c0 = 0.0;
+  int N_ = 0;
+  int chunk = 1;
+  std::vector<int> a_t, b_t;
+  std::vector<uint64_t> xs, zs;
+  std::vector<int64_t> order;
+  std::vector<Chunk> chunks;
+  DevBuf d_coeff, d_jobs, d_fin_slot, d_fin_term;
+  const double* d_coeff_ptr = nullptr;
+  const SweepJob* d_jobs_ptr = nullptr;
+  const int* d_fin_slot_ptr = nullptr;
+  const int* d_fin_term_ptr = nullptr;
+  void upload_from(const mps_paulisum* h, int N, int dcap, hipStream_t s, size_t budget);
+};
+
+struct mps_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  size_t shm_set = 0;
+  size_t sweep_budget = (size_t)6 << 30;   // bytes for per-term environments
+  int last_degen_grad = 0;
+  GateWork gw{};
+  SweepBuffers sb{};
+  DevBuf b_C, b_A, b_V, b_sv, b_perm, b_gmeta, b_gdmeta, b_rot, b_stats, b_theta;
+  DevBuf b_Lid, b_Rid, b_Lslots, b_Y, b_Yid, b_energy, b_termval;
+  ~mps_ctx();
+  void set_device();
+  void ensure_gate_work(int dcap, const mps_trunc& tr, int max_sweeps);
+  void ensure_sweep(int N, int dcap, int chunk);
+  void reset_stats();
+};
+
+struct mps_state {
+  mps_ctx* ctx = nullptr;
+  int N = 0;
+  int dcap = 0;
+  mps_trunc trunc{};
+  DevBuf B, dims, lam, occ;
+};
+
+// A plan: the working state, the circuit, the Hamiltonian, the checkpoints of
+// the last forward pass and the buffers of the reverse pass.
+struct mps_plan {
+  mps_ctx* ctx = nullptr;
+  int N = 0;
+  int n_theta = 0;
+  mps_trunc trunc{};
+  mps_grad_opts opts{256, 0.0, 64, 0};
+  std::vector<uint8_t> occ_h;
+  mps_state* state = nullptr;      // working state
+  mps_state* replay = nullptr;     // state used to recompute a segment
+  DevCircuit C;
+  DevHamiltonian H;
+  DevBuf theta, grad, gphi;
+  DevBuf ckpt;                     // [n_seg][B | dims | lam] snapshots
+  size_t ckpt_stride = 0;
+  int n_seg = 0;
+  double E = 0.0, Z = 1.0, Eim = 0.0;
+  // reverse pass
+  DevBuf Bbar, lambar;             // cotangents of the site tensors and Schmidt vectors
+  DevBuf tape;                     // per-gate records of one segment
+  DevBuf work;                     // per-gate adjoint workspace
+  DevBuf sweep_work;               // sweep-adjoint buffers
+  ~mps_plan();
+};
