@@ -1,8 +1,1043 @@
-// Reverse pass (filled in below).
+// Reverse pass of the MPS energy (arXiv:2211.07983, Sec. 4 and App. A).
+//
+// The loss E(theta) = <psi|H|psi>/<psi|psi> is differentiated through every
+// elementary step of the forward pass -- the "local" gradient that Sec. 4
+// discusses -- using the complex back-propagation rules of App. A (Eqs.
+// bp1-bp4).  A cotangent X_bar of a complex array X is defined by
+// dE = Re <X_bar, dX> = Re sum conj(X_bar) dX (the paper's 2 dE/dX* rule).
+//
+// S7 (sweep adjoint): X_bar_n = (2/Z) [sum_k c_k G^(k)_n - (E - c0) G^id_n] with
+//   G^i = conj(o_i) L B^{i^x} R^T, per term inside its support and through
+//   aggregated environments outside it.
+// S8 (gate adjoint): for each gate in reverse order, recomputed from the last
+//   checkpoint with a tape, the adjoints of the site update, of the truncated
+//   SVD (full spectrum: F_ij = 1/(s_j^2 - s_i^2), the imaginary diagonal gauge
+//   term and the null space) and of the contraction; dE/dphi = Re <C_bar, D C>
+//   with D = dQ/dphi Q^dagger = -(i/2) post ZZ post^dagger.
+// S9: dE/dtheta_p = sum over gates with param p of coeff * dE/dphi.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "engine.h"
 #include "plan_impl.h"
 
+void plan_restore(mps_plan* p, int seg, mps_state* dst);
+
+// ============================================================================
+// Environment transfers with per-job pointers (sweep adjoint)
+// ============================================================================
+struct EnvJob {
+  const zd* in;   // input environment
+  zd* out;        // output environment
+  zd* y;          // stage-1 buffer ([dc][2 dc])
+  const zd* rr;   // right environment of the contribution
+  zd* g;          // contribution buffer ([dc][2 dc])
+  double c;       // term coefficient
+  int xb;         // bit flip of the site operator
+  int acc;        // stage 2 accumulates into out
+  zd o0, o1;      // O[i^x, i] = o_i
+};
+
+// Y = in [B^0 | B^1] (a x 2b), column c = i*b + beta
+__global__ __launch_bounds__(256) void k_env_left1(const EnvJob* jobs, const zd* B, int a, int b, int dc) {
+  const EnvJob jb = jobs[blockIdx.z];
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  if (i0 >= a || j0 >= 2 * b) return;
+  auto fa = [&](int r, int k) { return jb.in[(size_t)r * dc + k]; };
+  auto fb = [&](int k, int c) {
+    const int i = c >= b, be = c - i * b;
+    return B[(size_t)k * 2 * dc + i * dc + be];
+  };
+  zd acc[2][2];
+  ztile_acc(a, 2 * b, a, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int r = r0 + x, c = c0 + y;
+      if (r < a && c < 2 * b) {
+        const int i = c >= b, be = c - i * b;
+        jb.y[(size_t)r * 2 * dc + i * dc + be] = acc[x][y];
+      }
+    }
+}
+
+// out[b', b] (+)= sum_{i, a'} o_i conj(B^{i^x}[a', b']) Y[a', i, b]
+__global__ __launch_bounds__(256) void k_env_left2(const EnvJob* jobs, const zd* B, int a, int b, int dc) {
+  const EnvJob jb = jobs[blockIdx.z];
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  if (i0 >= b || j0 >= b) return;
+  auto fa = [&](int r, int k) {
+    const int i = k >= a, al = k - i * a;
+    return zmul(i ? jb.o1 : jb.o0, zconj(B[(size_t)al * 2 * dc + (i ^ jb.xb) * dc + r]));
+  };
+  auto fb = [&](int k, int c) {
+    const int i = k >= a, al = k - i * a;
+    return jb.y[(size_t)al * 2 * dc + i * dc + c];
+  };
+  zd acc[2][2];
+  ztile_acc(b, b, 2 * a, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int r = r0 + x, c = c0 + y;
+      if (r < b && c < b) {
+        zd* o = jb.out + (size_t)r * dc + c;
+        *o = jb.acc ? zadd(*o, acc[x][y]) : acc[x][y];
+      }
+    }
+}
+
+// Yr[(i, a'), b] = sum_b' conj(B^{i^x}[a', b']) in[b', b]   (2a x b, ld dc)
+__global__ __launch_bounds__(256) void k_env_right1(const EnvJob* jobs, const zd* B, int a, int b, int dc) {
+  const EnvJob jb = jobs[blockIdx.z];
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  if (i0 >= 2 * a || j0 >= b) return;
+  auto fa = [&](int r, int k) {
+    const int i = r >= a, al = r - i * a;
+    return zconj(B[(size_t)al * 2 * dc + (i ^ jb.xb) * dc + k]);
+  };
+  auto fb = [&](int k, int c) { return jb.in[(size_t)k * dc + c]; };
+  zd acc[2][2];
+  ztile_acc(2 * a, b, b, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int r = r0 + x, c = c0 + y;
+      if (r < 2 * a && c < b) jb.y[(size_t)r * dc + c] = acc[x][y];
+    }
+}
+
+// out[a', a] (+)= sum_{i, b} o_i Yr[(i, a'), b] B^i[a, b]
+__global__ __launch_bounds__(256) void k_env_right2(const EnvJob* jobs, const zd* B, int a, int b, int dc) {
+  const EnvJob jb = jobs[blockIdx.z];
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  if (i0 >= a || j0 >= a) return;
+  auto fa = [&](int r, int k) {
+    const int i = k >= b, be = k - i * b;
+    return zmul(i ? jb.o1 : jb.o0, jb.y[(size_t)(i * a + r) * dc + be]);
+  };
+  auto fb = [&](int k, int c) {
+    const int i = k >= b, be = k - i * b;
+    return B[(size_t)c * 2 * dc + i * dc + be];
+  };
+  zd acc[2][2];
+  ztile_acc(a, a, 2 * b, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int r = r0 + x, c = c0 + y;
+      if (r < a && c < a) {
+        zd* o = jb.out + (size_t)r * dc + c;
+        *o = jb.acc ? zadd(*o, acc[x][y]) : acc[x][y];
+      }
+    }
+}
+
+// g[a][i][b] = c conj(o_i) sum_b' Y[a][i^x][b'] rr[b][b']
+__global__ __launch_bounds__(256) void k_env_contrib(const EnvJob* jobs, int a, int b, int dc) {
+  const EnvJob jb = jobs[blockIdx.z];
+  const int tiles_a = (a + ZT_M - 1) / ZT_M;
+  const int i = blockIdx.y / tiles_a;
+  const int i0 = (blockIdx.y % tiles_a) * ZT_M, j0 = blockIdx.x * ZT_N;
+  if (i0 >= a || j0 >= b) return;
+  const int src = i ^ jb.xb;
+  auto fa = [&](int r, int k) { return jb.y[(size_t)r * 2 * dc + src * dc + k]; };
+  auto fb = [&](int k, int c) { return jb.rr[(size_t)c * dc + k]; };
+  zd acc[2][2];
+  ztile_acc(a, b, b, i0, j0, fa, fb, acc);
+  const zd w = zscale(zconj(i ? jb.o1 : jb.o0), jb.c);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int r = r0 + x, c = c0 + y;
+      if (r < a && c < b) jb.g[(size_t)r * 2 * dc + i * dc + c] = zmul(w, acc[x][y]);
+    }
+}
+
+// Bbar_n[a][i][b] += sum_z g_z[a][i][b]  (fixed order)
+__global__ void k_env_reduce(const EnvJob* jobs, int nj, zd* Bbar, int a, int b, int dc) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a * 2 * b) return;
+  const int al = e / (2 * b), rem = e % (2 * b), i = rem / b, be = rem % b;
+  const size_t off = (size_t)al * 2 * dc + i * dc + be;
+  zd s = Bbar[off];
+  for (int z = 0; z < nj; ++z) s = zadd(s, jobs[z].g[off]);
+  Bbar[off] = s;
+}
+
+// dst[r][c] += sum_z coeff_z src_z[r][c] for r, c < d  (fixed order)
+struct InjectItem {
+  const zd* src;
+  double c;
+  double pad;
+};
+__global__ void k_inject(const InjectItem* items, int ni, zd* dst, int d, int dc) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d * d) return;
+  const size_t off = (size_t)(e / d) * dc + (e % d);
+  zd s = dst[off];
+  for (int z = 0; z < ni; ++z) s = zadd(s, zscale(items[z].src[off], items[z].c));
+  dst[off] = s;
+}
+
+__global__ void k_scale_sites(zd* Bbar, const int* dims, int N, int dc, double w) {
+  const int n = blockIdx.y;
+  const int a = dims[n], b = dims[n + 1];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < a * 2 * b; e += gridDim.x * blockDim.x) {
+    const int al = e / (2 * b), rem = e % (2 * b), i = rem / b, be = rem % b;
+    const size_t off = (size_t)n * dc * 2 * dc + (size_t)al * 2 * dc + i * dc + be;
+    Bbar[off] = zscale(Bbar[off], w);
+  }
+}
+
+// ============================================================================
+// Gate adjoint kernels (sizes known on the host from the tape)
+// ============================================================================
+struct GateRec {      // device pointers of one tape record
+  zd* Bl;
+  zd* Br;
+  double* lam;
+  zd* C;
+  zd* A;
+  zd* V;
+  double* sv;
+  int* perm;
+  int* meta;        // [0] = r, [4..6] = a, m, b
+  double* dmeta;    // [0] = nu
+};
+
+struct AdjWork {
+  zd* Wbar;   // [dc][ldw]
+  zd* Kt;     // [ncap][dc]
+  zd* Phi;    // [ncap][ldw]
+  zd* T;      // [2dc][ldw]
+  zd* Mbar;   // [2dc][ldw]
+  zd* Cbar;   // [2dc][ldw]
+  zd* Thb;    // [2dc][ldw]
+  double* sbar;   // [dc]
+  double* scal;   // [8]: nubar, kscale
+  double* dpart;  // [1024] dphi partial sums
+  int ldw;
+};
+
+struct GateDims {
+  int n, a, m, b, r;
+  double nu;
+};
+
+__global__ void k_tape_inputs(MpsView st, int n, zd* Bl, zd* Br, double* lam, int* meta) {
+  const int a = st.dims[n], m = st.dims[n + 1], b = st.dims[n + 2];
+  const int dc = st.dcap;
+  const size_t site = (size_t)dc * 2 * dc;
+  const zd* s0 = st.site(n);
+  const zd* s1 = st.site(n + 1);
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < site; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e / dc), col = (int)(e % dc);
+    const int l = row >> 1;
+    if (l < a && col < m) Bl[e] = s0[e];
+    if (l < m && col < b) Br[e] = s1[e];
+  }
+  if (blockIdx.x == 0) {
+    for (int q = threadIdx.x; q < a; q += blockDim.x) lam[q] = st.lam[(size_t)n * dc + q];
+    if (threadIdx.x == 0) {
+      meta[4] = a;
+      meta[5] = m;
+      meta[6] = b;
+    }
+  }
+}
+
+// A1: Wbar[mu, c] = sum_row conj(Bbar_n[row, mu]) / nu * C[row, c] + Bbar_{n+1}[mu, c]
+__global__ __launch_bounds__(256) void k_adj_wbar(GateRec R, AdjWork W, const zd* Bbn, const zd* Bbn1, GateDims d,
+                                                  int dc, int ldc) {
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  if (i0 >= d.r || j0 >= 2 * d.b) return;
+  const double inv = 1.0 / d.nu;
+  auto fa = [&](int mu, int row) {
+    return zscale(zconj(Bbn[(size_t)(row >> 1) * 2 * dc + (row & 1) * dc + mu]), inv);
+  };
+  auto fb = [&](int row, int c) { return R.C[(size_t)c * ldc + row]; };
+  zd acc[2][2];
+  ztile_acc(d.r, 2 * d.b, 2 * d.a, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int mu = r0 + x, c = c0 + y;
+      if (mu < d.r && c < 2 * d.b) {
+        const int jp = c / d.b, be = c % d.b;
+        W.Wbar[(size_t)mu * W.ldw + c] = zadd(acc[x][y], Bbn1[(size_t)mu * 2 * dc + jp * dc + be]);
+      }
+    }
+}
+
+// A2: nu_bar and s_bar of the kept values (one block)
+__global__ __launch_bounds__(256) void k_adj_scalars(GateRec R, AdjWork W, const zd* Bbn1, const double* lbar_out,
+                                                     GateDims d, int dc, int ldv) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double d1 = 0.0;
+  for (int e = t; e < d.r * 2 * d.b; e += 256) {
+    const int mu = e / (2 * d.b), c = e % (2 * d.b);
+    const int jp = c / d.b, be = c % d.b;
+    const zd g1 = zsub(W.Wbar[(size_t)mu * W.ldw + c], Bbn1[(size_t)mu * 2 * dc + jp * dc + be]);
+    const zd v = R.V[(size_t)R.perm[mu] * ldv + c];
+    d1 += g1.x * v.x - g1.y * v.y;
+  }
+  d1 = block_sum256(d1, red);
+  double d2 = 0.0;
+  for (int mu = t; mu < d.r; mu += 256) d2 += lbar_out[mu] * R.sv[R.perm[mu]];
+  d2 = block_sum256(d2, red);
+  const double nubar = -d1 / d.nu - d2 / (d.nu * d.nu);
+  for (int mu = t; mu < d.r; mu += 256) W.sbar[mu] = lbar_out[mu] / d.nu + nubar * R.sv[R.perm[mu]] / d.nu;
+  if (t == 0) W.scal[0] = nubar;
+}
+
+// A3: Kt[i, mu] = sum_c conj(P[c, i]) conj(Wbar[mu, c]),  P = V[:, perm]
+__global__ __launch_bounds__(256) void k_adj_K(GateRec R, AdjWork W, GateDims d, int dc, int ldv) {
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  const int nb = 2 * d.b;
+  if (i0 >= nb || j0 >= d.r) return;
+  auto fa = [&](int i, int c) { return zconj(R.V[(size_t)R.perm[i] * ldv + c]); };
+  auto fb = [&](int c, int mu) { return zconj(W.Wbar[(size_t)mu * W.ldw + c]); };
+  zd acc[2][2];
+  ztile_acc(nb, d.r, nb, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int i = r0 + x, mu = c0 + y;
+      if (i < nb && mu < d.r) W.Kt[(size_t)i * dc + mu] = acc[x][y];
+    }
+}
+
+// A4: kscale = max |Kt| (one block, deterministic)
+__global__ __launch_bounds__(256) void k_adj_kscale(AdjWork W, GateDims d, int dc) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double m = 0.0;
+  for (int e = t; e < 2 * d.b * d.r; e += 256) {
+    const int i = e / d.r, mu = e % d.r;
+    m = fmax(m, sqrt(zabs2(W.Kt[(size_t)i * dc + mu])));
+  }
+  red[t] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) W.scal[1] = red[0];
+}
+
+// A5: Phi (sorted basis), Gamma_ij / s_i of the complex SVD adjoint
+__global__ void k_adj_phi(GateRec R, AdjWork W, GateDims d, int dc, double eta, GateStats* st) {
+  const int nb = 2 * d.b;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * nb) return;
+  const int i = e / nb, j = e % nb;
+  const int r = d.r;
+  const double si = R.sv[R.perm[i]], sj = R.sv[R.perm[j]];
+  zd phi = zmk(0.0, 0.0);
+  if (i == j) {
+    if (i < r) {
+      const zd kii = W.Kt[(size_t)i * dc + i];
+      phi = zmk(W.sbar[i] / si, -kii.y / (si * si));
+    }
+  } else if (i < r || j < r) {
+    const zd kij = j < r ? W.Kt[(size_t)i * dc + j] : zmk(0.0, 0.0);
+    const zd kji = i < r ? W.Kt[(size_t)j * dc + i] : zmk(0.0, 0.0);
+    const zd aij = zsub(kij, zconj(kji));
+    if (fabs(sj - si) < 1e-10 * fmax(si, sj)) {
+      // exactly degenerate pair: the energy is invariant under rotations inside a
+      // kept block, so a_ij vanishes; one that does not has no finite derivative
+      if (sqrt(zabs2(aij)) > 1e-8 * W.scal[1]) atomicAdd(&st->degen_grad, 1);
+    } else {
+      const double dd = sj * sj - si * si;
+      const double F = eta > 0.0 ? dd / (dd * dd + eta * eta) : 1.0 / dd;
+      phi = zscale(aij, F);
+    }
+  }
+  W.Phi[(size_t)i * W.ldw + j] = phi;
+}
+
+// A6: T[row, j] = sum_i A[row, perm i] Phi[i, j]
+__global__ __launch_bounds__(256) void k_adj_T(GateRec R, AdjWork W, GateDims d, int ldc) {
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  const int M = 2 * d.a, nb = 2 * d.b;
+  if (i0 >= M || j0 >= nb) return;
+  auto fa = [&](int row, int i) { return R.A[(size_t)R.perm[i] * ldc + row]; };
+  auto fb = [&](int i, int j) { return W.Phi[(size_t)i * W.ldw + j]; };
+  zd acc[2][2];
+  ztile_acc(M, nb, nb, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y)
+      if (r0 + x < M && c0 + y < nb) W.T[(size_t)(r0 + x) * W.ldw + c0 + y] = acc[x][y];
+}
+
+// A7: Mbar[row, c] = sum_j T[row, j] conj(P[c, j])
+__global__ __launch_bounds__(256) void k_adj_Mbar(GateRec R, AdjWork W, GateDims d, int ldv) {
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  const int M = 2 * d.a, nb = 2 * d.b;
+  if (i0 >= M || j0 >= nb) return;
+  auto fa = [&](int row, int j) { return W.T[(size_t)row * W.ldw + j]; };
+  auto fb = [&](int j, int c) { return zconj(R.V[(size_t)R.perm[j] * ldv + c]); };
+  zd acc[2][2];
+  ztile_acc(M, nb, nb, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y)
+      if (r0 + x < M && c0 + y < nb) W.Mbar[(size_t)(r0 + x) * W.ldw + c0 + y] = acc[x][y];
+}
+
+// A8: Cbar[row, c] = sum_mu Bbar_n[row, mu]/nu conj(P[c, mu]) + lambda_in[alpha] Mbar[row, c]
+__global__ __launch_bounds__(256) void k_adj_Cbar(GateRec R, AdjWork W, const zd* Bbn, GateDims d, int dc, int ldv) {
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  const int M = 2 * d.a, nb = 2 * d.b;
+  if (i0 >= M || j0 >= nb) return;
+  const double inv = 1.0 / d.nu;
+  auto fa = [&](int row, int mu) {
+    return zscale(Bbn[(size_t)(row >> 1) * 2 * dc + (row & 1) * dc + mu], inv);
+  };
+  auto fb = [&](int mu, int c) { return zconj(R.V[(size_t)R.perm[mu] * ldv + c]); };
+  zd acc[2][2];
+  ztile_acc(M, nb, d.r, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int row = r0 + x, c = c0 + y;
+      if (row < M && c < nb) {
+        const size_t o = (size_t)row * W.ldw + c;
+        W.Cbar[o] = zadd(acc[x][y], zscale(W.Mbar[o], R.lam[row >> 1]));
+      }
+    }
+}
+
+// A9: lambar_{n-1}[alpha] += Re sum conj(Mbar[(alpha,i'), c]) C[(alpha,i'), c]
+__global__ __launch_bounds__(256) void k_adj_lambar(GateRec R, AdjWork W, GateDims d, double* lbar_in, int ldc) {
+  __shared__ double red[256];
+  const int al = blockIdx.x;
+  const int nb = 2 * d.b;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < 2 * nb; e += 256) {
+    const int ip = e / nb, c = e % nb;
+    const int row = 2 * al + ip;
+    const zd mb = W.Mbar[(size_t)row * W.ldw + c], cc = R.C[(size_t)c * ldc + row];
+    s += mb.x * cc.x + mb.y * cc.y;
+  }
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) lbar_in[al] += s;
+}
+
+// A10: Theta_bar = Q^dagger C_bar on (i', j'); dphi partial sums Re <C_bar, D C>
+__global__ __launch_bounds__(256) void k_adj_theta(GateRec R, AdjWork W, GateTable gt, int g, const double* theta,
+                                                   GateDims d, int ldc) {
+  __shared__ zd Q[16];
+  __shared__ zd D[16];
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  gate_matrix(gt, g, theta, Q);
+  const bool param = gt.kind[g] == 1;
+  if (param && t < 16) {
+    // D = -(i/2) post ZZ post^dagger
+    const zd* post = gt.post + (size_t)g * 16;
+    const int r = t >> 2, c = t & 3;
+    zd acc = zmk(0.0, 0.0);
+    for (int k = 0; k < 4; ++k) {
+      const double zz = (k == 0 || k == 3) ? 1.0 : -1.0;
+      acc = zfma(zscale(post[r * 4 + k], zz), zconj(post[c * 4 + k]), acc);
+    }
+    D[t] = zmk(0.5 * acc.y, -0.5 * acc.x);
+  }
+  __syncthreads();
+  const int e = blockIdx.x * 256 + t;
+  double part = 0.0;
+  if (e < d.a * d.b) {
+    const int al = e / d.b, be = e % d.b;
+    zd cb[4], cc[4];
+    for (int ip = 0; ip < 2; ++ip)
+      for (int jp = 0; jp < 2; ++jp) {
+        const int row = 2 * al + ip, col = jp * d.b + be;
+        cb[ip * 2 + jp] = W.Cbar[(size_t)row * W.ldw + col];
+        cc[ip * 2 + jp] = R.C[(size_t)col * ldc + row];
+      }
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        zd v = zmk(0.0, 0.0);
+        for (int k = 0; k < 4; ++k) v = zfmac(Q[k * 4 + i * 2 + j], cb[k], v);
+        W.Thb[(size_t)(2 * al + i) * W.ldw + j * d.b + be] = v;
+      }
+    if (param)
+      for (int k = 0; k < 4; ++k) {
+        zd dc_ = zmk(0.0, 0.0);
+        for (int l = 0; l < 4; ++l) dc_ = zfma(D[k * 4 + l], cc[l], dc_);
+        part += cb[k].x * dc_.x + cb[k].y * dc_.y;
+      }
+  }
+  part = block_sum256(part, red);
+  if (t == 0) W.dpart[blockIdx.x] = part;
+}
+
+// A11: Bbar_n[(alpha,i), gamma] = sum_c Theta_bar[(alpha,i), c] conj(B_{n+1}[gamma, c])
+__global__ __launch_bounds__(256) void k_adj_Bl(GateRec R, AdjWork W, zd* Bbn, GateDims d, int dc) {
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  const int M = 2 * d.a;
+  if (i0 >= M || j0 >= d.m) return;
+  auto fa = [&](int row, int c) { return W.Thb[(size_t)row * W.ldw + c]; };
+  auto fb = [&](int c, int ga) {
+    const int jp = c / d.b, be = c % d.b;
+    return zconj(R.Br[(size_t)ga * 2 * dc + jp * dc + be]);
+  };
+  zd acc[2][2];
+  ztile_acc(M, d.m, 2 * d.b, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int row = r0 + x, ga = c0 + y;
+      if (row < M && ga < d.m) Bbn[(size_t)(row >> 1) * 2 * dc + (row & 1) * dc + ga] = acc[x][y];
+    }
+}
+
+// A12: Bbar_{n+1}[gamma, c] = sum_row conj(B_n[row, gamma]) Theta_bar[row, c]
+__global__ __launch_bounds__(256) void k_adj_Br(GateRec R, AdjWork W, zd* Bbn1, GateDims d, int dc) {
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  const int nb = 2 * d.b;
+  if (i0 >= d.m || j0 >= nb) return;
+  auto fa = [&](int ga, int row) { return zconj(R.Bl[(size_t)(row >> 1) * 2 * dc + (row & 1) * dc + ga]); };
+  auto fb = [&](int row, int c) { return W.Thb[(size_t)row * W.ldw + c]; };
+  zd acc[2][2];
+  ztile_acc(d.m, nb, 2 * d.a, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int ga = r0 + x, c = c0 + y;
+      if (ga < d.m && c < nb) {
+        const int jp = c / d.b, be = c % d.b;
+        Bbn1[(size_t)ga * 2 * dc + jp * dc + be] = acc[x][y];
+      }
+    }
+}
+
+// A13: lambar_n = 0 (the old lambda_n was overwritten by this gate); dE/dphi
+__global__ void k_adj_finish(AdjWork W, double* lbar_out, int dc, int nparts, double* gphi, int g, int param) {
+  for (int q = threadIdx.x; q < dc; q += blockDim.x) lbar_out[q] = 0.0;
+  if (threadIdx.x == 0 && param) {
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += W.dpart[k];
+    gphi[g] = s;
+  }
+}
+
+// S9: grad[p] = sum_{g: param_g = p} coeff_g gphi[g]  (fixed order per parameter)
+__global__ void k_chain_rule(const int* gstart, const int* glist, GateTable gt, const double* gphi, double* grad,
+                             int n_theta) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_theta) return;
+  double s = 0.0;
+  for (int k = gstart[p]; k < gstart[p + 1]; ++k) {
+    const int g = glist[k];
+    s += gt.coeff[g] * gphi[g];
+  }
+  grad[p] = s;
+}
+
+// ============================================================================
+// Host: sweep adjoint
+// ============================================================================
+static inline dim3 gemm_grid(int M, int N, int z = 1) {
+  return dim3((N + ZT_N - 1) / ZT_N, (M + ZT_M - 1) / ZT_M, z);
+}
+
+struct SweepAdjPlan {
+  bool built = false;
+  int dc = 0;
+  std::vector<int> dims;          // final MPS dims used to build
+  // per chunk, per site: job ranges in d_jobs
+  struct SiteJobs { size_t off = 0; int nj = 0; };
+  struct ChunkJobs {
+    int lo = 0, hi = -1;
+    std::vector<SiteJobs> right, left;
+    std::vector<SiteJobs> injR, injL;   // per site m (index m - lo), items in d_inj
+  };
+  std::vector<ChunkJobs> chunks;
+  std::vector<EnvJob> jobs_h;
+  std::vector<InjectItem> inj_h;
+  DevBuf d_jobs, d_inj, d_small;
+  DevBuf Rslots, Lslots, Y, Gb, Lagg, Ragg;
+  const zd* lid = nullptr;   // environment buffers the job pointers refer to
+  const zd* rid = nullptr;
+  int chunk_slots = 0;
+};
+
+struct PlanAdj {
+  SweepAdjPlan sw;
+  DevBuf chain_start, chain_list;
+  bool chain_built = false;
+};
+
+static PlanAdj& adj_of(mps_plan* p) {
+  if (!p->adj) p->adj = new PlanAdj();
+  return *(PlanAdj*)p->adj;
+}
+
+void plan_adj_free(void* a) { delete (PlanAdj*)a; }
+
+static zd* envp(zd* base, int dc, int k) { return base + (size_t)k * dc * dc; }
+
+static void build_sweep_adjoint(mps_plan* p, SweepAdjPlan& S, const std::vector<int>& dims) {
+  mps_ctx* ctx = p->ctx;
+  DevHamiltonian& H = p->H;
+  const int N = p->N;
+  const int dc = p->state->dcap;
+  const size_t dd = (size_t)dc * dc;
+  const int64_t K = H.K;
+  // chunking by memory: R slots (one per site of the support) + L slot + Y + G
+  const size_t budget = ctx->sweep_budget;
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  int max_slots = 0, max_terms = 0;
+  {
+    int64_t lo = 0;
+    size_t slots = 0;
+    for (int64_t j = 0; j < K; ++j) {
+      const int64_t k = H.order[j];
+      const size_t s = (size_t)(H.b_t[k] - H.a_t[k] + 1);
+      const size_t need = (slots + s + 5 * (size_t)(j - lo + 1)) * dd * sizeof(zd);
+      if (j > lo && (need > budget || j - lo >= 60000)) {
+        ranges.push_back({lo, j});
+        max_slots = std::max<int>(max_slots, (int)slots);
+        max_terms = std::max<int>(max_terms, (int)(j - lo));
+        lo = j;
+        slots = 0;
+      }
+      slots += s;
+    }
+    if (K > lo) {
+      ranges.push_back({lo, K});
+      max_slots = std::max<int>(max_slots, (int)slots);
+      max_terms = std::max<int>(max_terms, (int)(K - lo));
+    }
+  }
+  max_terms = std::max(max_terms, 3);
+  zd* Rs = (zd*)S.Rslots.ensure((size_t)std::max(1, max_slots) * dd * sizeof(zd));
+  zd* Ls = (zd*)S.Lslots.ensure((size_t)max_terms * dd * sizeof(zd));
+  zd* Yb = (zd*)S.Y.ensure((size_t)max_terms * 2 * dd * sizeof(zd));
+  zd* Gb = (zd*)S.Gb.ensure((size_t)max_terms * 2 * dd * sizeof(zd));
+  zd* Lagg = (zd*)S.Lagg.ensure((size_t)(N + 1) * dd * sizeof(zd));
+  zd* Ragg = (zd*)S.Ragg.ensure((size_t)(N + 1) * dd * sizeof(zd));
+  (void)Lagg;
+  (void)Ragg;
+  zd* Lid = ctx->sb.Lid;
+  zd* Rid = ctx->sb.Rid;
+  S.jobs_h.clear();
+  S.inj_h.clear();
+  S.chunks.clear();
+  for (auto& rg : ranges) {
+    SweepAdjPlan::ChunkJobs ch;
+    ch.lo = N;
+    ch.hi = -1;
+    std::vector<int> base(rg.second - rg.first);
+    int slots = 0;
+    for (int64_t j = rg.first; j < rg.second; ++j) {
+      const int64_t k = H.order[j];
+      ch.lo = std::min(ch.lo, H.a_t[k]);
+      ch.hi = std::max(ch.hi, H.b_t[k]);
+      base[j - rg.first] = slots;
+      slots += H.b_t[k] - H.a_t[k] + 1;
+    }
+    auto rslot = [&](int64_t j, int m) {   // R^{(k)}_m for m in [a_k, b_k]
+      const int64_t k = H.order[j];
+      return envp(Rs, dc, base[j - rg.first] + (m - H.a_t[k]));
+    };
+    auto phases = [&](int64_t k, int n, EnvJob& jb) {
+      const int xb = (H.xs[k] >> n) & 1, zb = (H.zs[k] >> n) & 1;
+      const zd base_ = (xb && zb) ? zmk(0.0, 1.0) : zmk(1.0, 0.0);
+      jb.xb = xb;
+      jb.o0 = base_;
+      jb.o1 = zb ? zmk(-base_.x, -base_.y) : base_;
+    };
+    const int ns = ch.hi - ch.lo + 1;
+    ch.right.resize(ns);
+    ch.left.resize(ns);
+    ch.injR.resize(ns);
+    ch.injL.resize(ns);
+    // right sweep: site m, R^{(k)}_m = T_m(R^{(k)}_{m+1})
+    for (int m = ch.hi; m >= ch.lo; --m) {
+      SweepAdjPlan::SiteJobs sj;
+      sj.off = S.jobs_h.size();
+      int z = 0;
+      for (int64_t j = rg.first; j < rg.second; ++j) {
+        const int64_t k = H.order[j];
+        if (!(H.a_t[k] <= m && m <= H.b_t[k])) continue;
+        EnvJob jb{};
+        jb.in = (m == H.b_t[k]) ? envp(Rid, dc, m + 1) : rslot(j, m + 1);
+        jb.out = rslot(j, m);
+        jb.y = Yb + (size_t)z * 2 * dd;
+        jb.acc = 0;
+        jb.c = H.coeff_h[k];
+        phases(k, m, jb);
+        S.jobs_h.push_back(jb);
+        ++z;
+      }
+      sj.nj = z;
+      ch.right[m - ch.lo] = sj;
+    }
+    // injections of rho_k = R^{(k)}_{a_k} into Ragg[a_k]
+    for (int m = ch.lo; m <= ch.hi; ++m) {
+      SweepAdjPlan::SiteJobs sj;
+      sj.off = S.inj_h.size();
+      for (int64_t j = rg.first; j < rg.second; ++j) {
+        const int64_t k = H.order[j];
+        if (H.a_t[k] == m) S.inj_h.push_back(InjectItem{rslot(j, m), H.coeff_h[k], 0.0});
+      }
+      sj.nj = (int)(S.inj_h.size() - sj.off);
+      ch.injR[m - ch.lo] = sj;
+    }
+    // left sweep with contributions; L slot per term
+    for (int n = ch.lo; n <= ch.hi; ++n) {
+      SweepAdjPlan::SiteJobs sj;
+      sj.off = S.jobs_h.size();
+      int z = 0;
+      for (int64_t j = rg.first; j < rg.second; ++j) {
+        const int64_t k = H.order[j];
+        if (!(H.a_t[k] <= n && n <= H.b_t[k])) continue;
+        EnvJob jb{};
+        zd* Lk = envp(Ls, dc, (int)(j - rg.first));
+        jb.in = (n == H.a_t[k]) ? envp(Lid, dc, n) : Lk;
+        jb.out = Lk;
+        jb.y = Yb + (size_t)z * 2 * dd;
+        jb.g = Gb + (size_t)z * 2 * dd;
+        jb.rr = (n == H.b_t[k]) ? envp(Rid, dc, n + 1) : rslot(j, n + 1);
+        jb.c = H.coeff_h[k];
+        jb.acc = 0;
+        phases(k, n, jb);
+        S.jobs_h.push_back(jb);
+        ++z;
+      }
+      sj.nj = z;
+      ch.left[n - ch.lo] = sj;
+      SweepAdjPlan::SiteJobs ij;
+      ij.off = S.inj_h.size();
+      for (int64_t j = rg.first; j < rg.second; ++j) {
+        const int64_t k = H.order[j];
+        if (H.b_t[k] == n) S.inj_h.push_back(InjectItem{envp(Ls, dc, (int)(j - rg.first)), H.coeff_h[k], 0.0});
+      }
+      ij.nj = (int)(S.inj_h.size() - ij.off);
+      ch.injL[n - ch.lo] = ij;
+    }
+    S.chunks.push_back(ch);
+  }
+  upload(S.d_jobs, S.jobs_h.data(), S.jobs_h.size(), ctx->stream);
+  upload(S.d_inj, S.inj_h.data(), S.inj_h.size(), ctx->stream);
+  S.d_small.ensure(16 * sizeof(EnvJob));
+  S.dims = dims;
+  S.dc = dc;
+  S.lid = Lid;
+  S.rid = Rid;
+  S.built = true;
+}
+
+static void run_sweep_adjoint(mps_plan* p, const std::vector<int>& dims) {
+  mps_ctx* ctx = p->ctx;
+  hipStream_t s = ctx->stream;
+  SweepAdjPlan& S = adj_of(p).sw;
+  if (!S.built || S.dims != dims || S.lid != ctx->sb.Lid || S.rid != ctx->sb.Rid) build_sweep_adjoint(p, S, dims);
+  const int N = p->N, dc = S.dc;
+  const size_t dd = (size_t)dc * dc;
+  zd* Bbar = (zd*)p->Bbar.p;
+  zd* Lagg = (zd*)S.Lagg.p;
+  zd* Ragg = (zd*)S.Ragg.p;
+  const zd* B = (const zd*)p->state->B.p;
+  const size_t site = (size_t)dc * 2 * dc;
+  HIPCHK(hipMemsetAsync(Bbar, 0, (size_t)N * site * sizeof(zd), s));
+  HIPCHK(hipMemsetAsync(Lagg, 0, (size_t)(N + 1) * dd * sizeof(zd), s));
+  HIPCHK(hipMemsetAsync(Ragg, 0, (size_t)(N + 1) * dd * sizeof(zd), s));
+  const EnvJob* J = (const EnvJob*)S.d_jobs.p;
+  const InjectItem* I = (const InjectItem*)S.d_inj.p;
+  for (auto& ch : S.chunks) {
+    for (int m = ch.hi; m >= ch.lo; --m) {
+      const auto& sj = ch.right[m - ch.lo];
+      const int a = dims[m], b = dims[m + 1];
+      if (sj.nj) {
+        hipLaunchKernelGGL(k_env_right1, gemm_grid(2 * a, b, sj.nj), dim3(256), 0, s, J + sj.off, B + (size_t)m * site, a, b, dc);
+        hipLaunchKernelGGL(k_env_right2, gemm_grid(a, a, sj.nj), dim3(256), 0, s, J + sj.off, B + (size_t)m * site, a, b, dc);
+      }
+    }
+    for (int m = ch.lo; m <= ch.hi; ++m) {
+      const auto& ij = ch.injR[m - ch.lo];
+      const int d = dims[m];
+      if (ij.nj) hipLaunchKernelGGL(k_inject, dim3((d * d + 255) / 256), dim3(256), 0, s, I + ij.off, ij.nj, Ragg + (size_t)m * dd, d, dc);
+    }
+    for (int n = ch.lo; n <= ch.hi; ++n) {
+      const auto& sj = ch.left[n - ch.lo];
+      const int a = dims[n], b = dims[n + 1];
+      const zd* Bn = B + (size_t)n * site;
+      if (sj.nj) {
+        hipLaunchKernelGGL(k_env_left1, gemm_grid(a, 2 * b, sj.nj), dim3(256), 0, s, J + sj.off, Bn, a, b, dc);
+        const int ta = (a + ZT_M - 1) / ZT_M;
+        hipLaunchKernelGGL(k_env_contrib, dim3((b + ZT_N - 1) / ZT_N, 2 * ta, sj.nj), dim3(256), 0, s, J + sj.off, a, b, dc);
+        hipLaunchKernelGGL(k_env_reduce, dim3((a * 2 * b + 255) / 256), dim3(256), 0, s, J + sj.off, sj.nj,
+                           Bbar + (size_t)n * site, a, b, dc);
+        hipLaunchKernelGGL(k_env_left2, gemm_grid(b, b, sj.nj), dim3(256), 0, s, J + sj.off, Bn, a, b, dc);
+      }
+      const auto& ij = ch.injL[n - ch.lo];
+      const int d = dims[n + 1];
+      if (ij.nj) hipLaunchKernelGGL(k_inject, dim3((d * d + 255) / 256), dim3(256), 0, s, I + ij.off, ij.nj, Lagg + (size_t)(n + 1) * dd, d, dc);
+    }
+  }
+  // aggregated environments outside the supports, and the Z term
+  zd* Yb = (zd*)S.Y.p;
+  zd* Gb = (zd*)S.Gb.p;
+  EnvJob* dj = (EnvJob*)S.d_small.p;
+  std::vector<EnvJob> hj(3);
+  const zd one = zmk(1.0, 0.0);
+  // Lagg_{m+1} += T_m(Lagg_m)
+  for (int m = 0; m < N; ++m) {
+    const int a = dims[m], b = dims[m + 1];
+    EnvJob jb{};
+    jb.in = Lagg + (size_t)m * dd;
+    jb.out = Lagg + (size_t)(m + 1) * dd;
+    jb.y = Yb;
+    jb.acc = 1;
+    jb.o0 = one;
+    jb.o1 = one;
+    HIPCHK(hipMemcpyAsync(dj + 0, &jb, sizeof(EnvJob), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_env_left1, gemm_grid(a, 2 * b), dim3(256), 0, s, dj, B + (size_t)m * site, a, b, dc);
+    hipLaunchKernelGGL(k_env_left2, gemm_grid(b, b), dim3(256), 0, s, dj, B + (size_t)m * site, a, b, dc);
+    HIPCHK(hipStreamSynchronize(s));   // dj is reused
+  }
+  for (int m = N - 1; m >= 0; --m) {
+    const int a = dims[m], b = dims[m + 1];
+    EnvJob jb{};
+    jb.in = Ragg + (size_t)(m + 1) * dd;
+    jb.out = Ragg + (size_t)m * dd;
+    jb.y = Yb;
+    jb.acc = 1;
+    jb.o0 = one;
+    jb.o1 = one;
+    HIPCHK(hipMemcpyAsync(dj + 0, &jb, sizeof(EnvJob), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_env_right1, gemm_grid(2 * a, b), dim3(256), 0, s, dj, B + (size_t)m * site, a, b, dc);
+    hipLaunchKernelGGL(k_env_right2, gemm_grid(a, a), dim3(256), 0, s, dj, B + (size_t)m * site, a, b, dc);
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  const double zc = -(p->E - p->H.c0);
+  for (int n = 0; n < N; ++n) {
+    const int a = dims[n], b = dims[n + 1];
+    const zd* Bn = B + (size_t)n * site;
+    for (int q = 0; q < 3; ++q) {
+      EnvJob jb{};
+      jb.y = Yb + (size_t)(q == 0 ? 0 : 1) * 2 * dd;
+      jb.g = Gb + (size_t)q * 2 * dd;
+      jb.o0 = one;
+      jb.o1 = one;
+      jb.c = q == 2 ? zc : 1.0;
+      jb.in = q == 0 ? Lagg + (size_t)n * dd : ctx->sb.Lid + (size_t)n * dd;
+      jb.rr = q == 1 ? Ragg + (size_t)(n + 1) * dd : ctx->sb.Rid + (size_t)(n + 1) * dd;
+      hj[q] = jb;
+    }
+    HIPCHK(hipMemcpyAsync(dj, hj.data(), 3 * sizeof(EnvJob), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_env_left1, gemm_grid(a, 2 * b, 2), dim3(256), 0, s, dj, Bn, a, b, dc);
+    const int ta = (a + ZT_M - 1) / ZT_M;
+    hipLaunchKernelGGL(k_env_contrib, dim3((b + ZT_N - 1) / ZT_N, 2 * ta, 3), dim3(256), 0, s, dj, a, b, dc);
+    hipLaunchKernelGGL(k_env_reduce, dim3((a * 2 * b + 255) / 256), dim3(256), 0, s, dj, 3, Bbar + (size_t)n * site, a, b, dc);
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  hipLaunchKernelGGL(k_scale_sites, dim3(64, N), dim3(256), 0, s, Bbar, (const int*)p->state->dims.p, N, dc,
+                     2.0 / p->Z);
+  HIPCHK(hipGetLastError());
+}
+
+// ============================================================================
+// Host: gate adjoint over checkpoint segments
+// ============================================================================
+struct TapeLayout {
+  size_t oBl, oBr, olam, oC, oA, oV, osv, operm, ometa, odmeta, rec;
+};
+
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+static TapeLayout tape_layout(int dc, int ncap, int ldc, int ldv) {
+  TapeLayout L;
+  size_t o = 0;
+  const size_t site = (size_t)dc * 2 * dc * sizeof(zd);
+  L.oBl = o; o = al256(o + site);
+  L.oBr = o; o = al256(o + site);
+  L.olam = o; o = al256(o + dc * sizeof(double));
+  L.oC = o; o = al256(o + (size_t)ncap * ldc * sizeof(zd));
+  L.oA = o; o = al256(o + (size_t)ncap * ldc * sizeof(zd));
+  L.oV = o; o = al256(o + (size_t)ncap * ldv * sizeof(zd));
+  L.osv = o; o = al256(o + ncap * sizeof(double));
+  L.operm = o; o = al256(o + ncap * sizeof(int));
+  L.ometa = o; o = al256(o + 16 * sizeof(int));
+  L.odmeta = o; o = al256(o + 16 * sizeof(double));
+  L.rec = o;
+  return L;
+}
+
+static GateRec rec_at(char* base, const TapeLayout& L, int k) {
+  char* r = base + (size_t)k * L.rec;
+  GateRec R;
+  R.Bl = (zd*)(r + L.oBl);
+  R.Br = (zd*)(r + L.oBr);
+  R.lam = (double*)(r + L.olam);
+  R.C = (zd*)(r + L.oC);
+  R.A = (zd*)(r + L.oA);
+  R.V = (zd*)(r + L.oV);
+  R.sv = (double*)(r + L.osv);
+  R.perm = (int*)(r + L.operm);
+  R.meta = (int*)(r + L.ometa);
+  R.dmeta = (double*)(r + L.odmeta);
+  return R;
+}
+
+static void build_chain(mps_plan* p, PlanAdj& A) {
+  std::vector<int> start(p->n_theta + 1, 0), list;
+  std::vector<std::vector<int>> per(p->n_theta);
+  for (int g = 0; g < p->C.G; ++g)
+    if (p->C.kind_h[g] == 1) per[p->C.param_h[g]].push_back(g);
+  for (int q = 0; q < p->n_theta; ++q) {
+    start[q] = (int)list.size();
+    list.insert(list.end(), per[q].begin(), per[q].end());
+  }
+  start[p->n_theta] = (int)list.size();
+  upload(A.chain_start, start.data(), start.size(), p->ctx->stream);
+  upload(A.chain_list, list.data(), std::max<size_t>(1, list.size()), p->ctx->stream);
+  A.chain_built = true;
+}
+
 void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
-  (void)p; (void)grad; (void)on_device; (void)stats;
-  fail(MPS_EINVAL, "reverse pass not built");
+  mps_ctx* ctx = p->ctx;
+  hipStream_t s = ctx->stream;
+  PlanAdj& A = adj_of(p);
+  mps_state* st = p->state;
+  const int N = p->N, dc = st->dcap;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  // final dims
+  std::vector<int> dims(N + 1);
+  HIPCHK(hipMemcpyAsync(dims.data(), st->dims.p, (N + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const size_t site = (size_t)dc * 2 * dc;
+  p->Bbar.ensure((size_t)N * site * sizeof(zd));
+  p->lambar.ensure((size_t)(N + 1) * dc * sizeof(double));
+  HIPCHK(hipMemsetAsync(p->lambar.p, 0, p->lambar.bytes, s));
+  run_sweep_adjoint(p, dims);
+  // ---- gate adjoint
+  GateWork gw = ctx->gw;
+  const TapeLayout L = tape_layout(dc, gw.ncap, gw.ldc, gw.ldv);
+  const int K = p->opts.ckpt_gates;
+  char* tape = (char*)p->tape.ensure((size_t)K * L.rec);
+  const int ldw = gw.ncap;
+  AdjWork W;
+  {
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = al256(o + bytes); return r; };
+    const size_t zm = (size_t)gw.ncap * ldw * sizeof(zd);
+    const size_t oW = take(zm), oK = take((size_t)gw.ncap * dc * sizeof(zd)), oP = take(zm), oT = take(zm),
+                 oM = take(zm), oCb = take(zm), oTh = take(zm), oS = take(dc * sizeof(double)),
+                 oSc = take(8 * sizeof(double)), oD = take(1024 * sizeof(double));
+    char* w = (char*)p->work.ensure(o);
+    W.Wbar = (zd*)(w + oW);
+    W.Kt = (zd*)(w + oK);
+    W.Phi = (zd*)(w + oP);
+    W.T = (zd*)(w + oT);
+    W.Mbar = (zd*)(w + oM);
+    W.Cbar = (zd*)(w + oCb);
+    W.Thb = (zd*)(w + oTh);
+    W.sbar = (double*)(w + oS);
+    W.scal = (double*)(w + oSc);
+    W.dpart = (double*)(w + oD);
+    W.ldw = ldw;
+  }
+  double* gphi = (double*)p->gphi.ensure((size_t)std::max(1, p->C.G) * sizeof(double));
+  HIPCHK(hipMemsetAsync(gphi, 0, p->gphi.bytes, s));
+  GateStats* scratch = (GateStats*)ctx->b_stats2.ensure(sizeof(GateStats));
+  zd* Bbar = (zd*)p->Bbar.p;
+  double* lambar = (double*)p->lambar.p;
+  mps_state* rp = p->replay;
+  MpsView rv = view_of(rp);
+  const double* th = (const double*)p->theta.p;
+  std::vector<int> meta(16);
+  std::vector<double> dmeta(16);
+  for (int sg = p->n_seg - 1; sg >= 0; --sg) {
+    const int g0 = sg * K, g1 = std::min(p->C.G, (sg + 1) * K);
+    plan_restore(p, sg, rp);
+    HIPCHK(hipMemsetAsync(scratch, 0, sizeof(GateStats), s));
+    for (int g = g0; g < g1; ++g) {
+      GateRec R = rec_at(tape, L, g - g0);
+      const int n = p->C.bond_h[g];
+      hipLaunchKernelGGL(k_tape_inputs, dim3(64), dim3(256), 0, s, rv, n, R.Bl, R.Br, R.lam, R.meta);
+      GateWork tw = gw;
+      tw.C = R.C;
+      tw.A = R.A;
+      tw.V = R.V;
+      tw.sv = R.sv;
+      tw.perm = R.perm;
+      tw.gmeta = R.meta;
+      tw.gdmeta = R.dmeta;
+      tw.stats = scratch;
+      HIPCHK(launch_gate(rv, p->C.tab, g, n, th, tw, s));
+    }
+    // sizes of the segment's gates
+    std::vector<GateDims> gd(g1 - g0);
+    for (int g = g0; g < g1; ++g) {
+      GateRec R = rec_at(tape, L, g - g0);
+      HIPCHK(hipMemcpyAsync(meta.data(), R.meta, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(dmeta.data(), R.dmeta, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      GateDims d;
+      d.n = p->C.bond_h[g];
+      d.r = meta[0];
+      d.a = meta[4];
+      d.m = meta[5];
+      d.b = meta[6];
+      d.nu = dmeta[0];
+      gd[g - g0] = d;
+    }
+    for (int g = g1 - 1; g >= g0; --g) {
+      GateRec R = rec_at(tape, L, g - g0);
+      const GateDims d = gd[g - g0];
+      const int n = d.n;
+      zd* Bbn = Bbar + (size_t)n * site;
+      zd* Bbn1 = Bbar + (size_t)(n + 1) * site;
+      double* lb_out = lambar + (size_t)(n + 1) * dc;
+      double* lb_in = lambar + (size_t)n * dc;
+      const int M = 2 * d.a, nb = 2 * d.b;
+      hipLaunchKernelGGL(k_adj_wbar, gemm_grid(d.r, nb), dim3(256), 0, s, R, W, (const zd*)Bbn, (const zd*)Bbn1, d, dc, gw.ldc);
+      hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, s, R, W, (const zd*)Bbn1, (const double*)lb_out, d, dc, gw.ldv);
+      hipLaunchKernelGGL(k_adj_K, gemm_grid(nb, d.r), dim3(256), 0, s, R, W, d, dc, gw.ldv);
+      hipLaunchKernelGGL(k_adj_kscale, dim3(1), dim3(256), 0, s, W, d, dc);
+      hipLaunchKernelGGL(k_adj_phi, dim3((nb * nb + 255) / 256), dim3(256), 0, s, R, W, d, dc, p->opts.broaden, gw.stats);
+      hipLaunchKernelGGL(k_adj_T, gemm_grid(M, nb), dim3(256), 0, s, R, W, d, gw.ldc);
+      hipLaunchKernelGGL(k_adj_Mbar, gemm_grid(M, nb), dim3(256), 0, s, R, W, d, gw.ldv);
+      hipLaunchKernelGGL(k_adj_Cbar, gemm_grid(M, nb), dim3(256), 0, s, R, W, (const zd*)Bbn, d, dc, gw.ldv);
+      hipLaunchKernelGGL(k_adj_lambar, dim3(d.a), dim3(256), 0, s, R, W, d, lb_in, gw.ldc);
+      const int nparts = (d.a * d.b + 255) / 256;
+      hipLaunchKernelGGL(k_adj_theta, dim3(nparts), dim3(256), 0, s, R, W, p->C.tab, g, th, d, gw.ldc);
+      hipLaunchKernelGGL(k_adj_Bl, gemm_grid(M, d.m), dim3(256), 0, s, R, W, Bbn, d, dc);
+      hipLaunchKernelGGL(k_adj_Br, gemm_grid(d.m, nb), dim3(256), 0, s, R, W, Bbn1, d, dc);
+      hipLaunchKernelGGL(k_adj_finish, dim3(1), dim3(256), 0, s, W, lb_out, dc, nparts, gphi, g, p->C.kind_h[g]);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  if (!A.chain_built) build_chain(p, A);
+  double* gd_dev = (double*)p->grad.ensure((size_t)std::max(1, p->n_theta) * sizeof(double));
+  hipLaunchKernelGGL(k_chain_rule, dim3((p->n_theta + 255) / 256), dim3(256), 0, s, (const int*)A.chain_start.p,
+                     (const int*)A.chain_list.p, p->C.tab, (const double*)gphi, gd_dev, p->n_theta);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(e1, s));
+  if (p->n_theta > 0)
+    HIPCHK(hipMemcpyAsync(grad, gd_dev, p->n_theta * sizeof(double),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  GateStats gs;
+  HIPCHK(hipMemcpyAsync(&gs, gw.stats, sizeof(GateStats), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (stats) stats->t_backward_ms = ms;
+  if (gs.degen_grad > 0 && p->opts.strict_degenerate)
+    fail(MPS_EDEGEN, std::to_string(gs.degen_grad) + " degenerate singular pairs carry a cotangent");
 }

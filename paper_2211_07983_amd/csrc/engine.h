@@ -41,6 +41,7 @@ struct GateWork {
   int* gmeta;     // [4]
   double* gdmeta; // [4]
   int* rotflag;   // [128]
+  double* nrm_part; // [256] per-tile |A|^2 partial sums of k_contract
   GateStats* stats;
   int ldc, ldv, ncap;
   double eps, tol;
@@ -65,7 +66,38 @@ struct SvdArgs {
   int dmax;
   double tol;
   int max_sweeps;
+  const double* nrm_part;
+  int nparts;
 };
+
+// ----------------------------------------------------------------------------
+// Gate matrix Q (4x4) of gate g, evaluated on the device from theta.
+// ----------------------------------------------------------------------------
+__device__ inline void gate_matrix(const GateTable& gt, int g, const double* theta, zd* Q) {
+  // called by threads 0..15 of a block, Q in shared memory
+  const int t = threadIdx.x;
+  const zd* pre = gt.pre + (size_t)g * 16;
+  if (gt.kind[g] == 0) {
+    if (t < 16) Q[t] = pre[t];
+    return;
+  }
+  const zd* post = gt.post + (size_t)g * 16;
+  const double phi = gt.coeff[g] * theta[gt.param[g]];
+  double sn, cs;
+  sincos(0.5 * phi, &sn, &cs);
+  // RZZ diagonal: e^{-i phi/2}, e^{+i phi/2}, e^{+i phi/2}, e^{-i phi/2}
+  if (t < 16) {
+    const int r = t >> 2, c = t & 3;
+    zd acc = zmk(0.0, 0.0);
+    for (int k = 0; k < 4; ++k) {
+      const double sg = (k == 0 || k == 3) ? -1.0 : 1.0;
+      const zd d = zmk(cs, sg * sn);
+      acc = zfma(zmul(post[r * 4 + k], d), pre[k * 4 + c], acc);
+    }
+    Q[t] = acc;
+  }
+}
+
 
 int svd_width(int dcap);
 hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, const double* theta,

@@ -60,11 +60,12 @@ void mps_ctx::ensure_gate_work(int dcap, const mps_trunc& tr, int max_sweeps) {
   gw.gmeta = (int*)b_gmeta.ensure(16 * sizeof(int));
   gw.gdmeta = (double*)b_gdmeta.ensure(16 * sizeof(double));
   gw.rotflag = (int*)b_rot.ensure(128 * sizeof(int));
+  gw.nrm_part = (double*)b_nrm.ensure(256 * sizeof(double));
   gw.stats = (GateStats*)b_stats.ensure(sizeof(GateStats));
   gw.eps = tr.eps;
   gw.dmax = tr.d_max;
   gw.max_sweeps = std::min(std::max(max_sweeps, 1), 100);   // per-sweep counters: 128 slots
-  gw.tol = std::max(1e-15, 2.0 * std::sqrt((double)ldc) * 2.220446049250313e-16);
+  gw.tol = std::max(1e-15, 8.0 * std::sqrt((double)ldc) * 2.220446049250313e-16);
   const size_t shm = (size_t)2 * W * (ldc + ncap) * sizeof(zd);
   if (shm > shm_set) {
     HIPCHK(svd_set_attributes(dcap, shm));
@@ -196,6 +197,7 @@ void DevHamiltonian::upload_from(const mps_paulisum* h, int N, int dcap, hipStre
     coeff[k] = h->coeff[k];
   }
   d_coeff_ptr = upload(d_coeff, coeff.data(), K, s);
+  coeff_h = coeff;
   // terms sorted by (first site, last site) and cut into chunks that fit the budget
   order.resize(K);
   for (int64_t k = 0; k < K; ++k) order[k] = k;

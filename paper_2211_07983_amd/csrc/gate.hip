@@ -13,47 +13,24 @@
 namespace cg = cooperative_groups;
 
 // ----------------------------------------------------------------------------
-// Gate matrix Q (4x4) of gate g, evaluated on the device from theta.
-// ----------------------------------------------------------------------------
-__device__ inline void gate_matrix(const GateTable& gt, int g, const double* theta, zd* Q) {
-  // called by threads 0..15 of a block, Q in shared memory
-  const int t = threadIdx.x;
-  const zd* pre = gt.pre + (size_t)g * 16;
-  if (gt.kind[g] == 0) {
-    if (t < 16) Q[t] = pre[t];
-    return;
-  }
-  const zd* post = gt.post + (size_t)g * 16;
-  const double phi = gt.coeff[g] * theta[gt.param[g]];
-  double sn, cs;
-  sincos(0.5 * phi, &sn, &cs);
-  // RZZ diagonal: e^{-i phi/2}, e^{+i phi/2}, e^{+i phi/2}, e^{-i phi/2}
-  if (t < 16) {
-    const int r = t >> 2, c = t & 3;
-    zd acc = zmk(0.0, 0.0);
-    for (int k = 0; k < 4; ++k) {
-      const double sg = (k == 0 || k == 3) ? -1.0 : 1.0;
-      const zd d = zmk(cs, sg * sn);
-      acc = zfma(zmul(post[r * 4 + k], d), pre[k * 4 + c], acc);
-    }
-    Q[t] = acc;
-  }
-}
-
-// ----------------------------------------------------------------------------
 // k_contract: C[(a,i'),(j',b)] = sum_{ij} Q[(i'j'),(ij)] sum_g B_n[a,i,g] B_{n+1}[g,j,b]
 // and A = lambda_{n-1}[a] C.  GEMM rows r = 2a + i, columns c = 2b + j so that
 // each thread holds the four (i, j) values of one (alpha, beta) pair.
 // C and A are column-major with leading dimension ldc; column index j'*b + beta.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int g, const double* theta,
-                                                  zd* C, zd* A, int ldc) {
+                                                  zd* C, zd* A, int ldc, double* nrm_part) {
   __shared__ zd Q[16];
+  __shared__ double red[256];
   const int n = gt.bond[g];
   const int a = st.dims[n], m = st.dims[n + 1], b = st.dims[n + 2];
   const int Mr = 2 * a, Nc = 2 * b;
   const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
-  if (i0 >= Mr || j0 >= Nc) return;
+  const int part = blockIdx.y * gridDim.x + blockIdx.x;
+  if (i0 >= Mr || j0 >= Nc) {
+    if (threadIdx.x == 0) nrm_part[part] = 0.0;
+    return;
+  }
   gate_matrix(gt, g, theta, Q);
   const zd* Bl = st.site(n);
   const zd* Br = st.site(n + 1);
@@ -64,18 +41,24 @@ __global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int 
   ztile_acc(Mr, Nc, m, i0, j0, fa, fb, acc);
   __syncthreads();
   const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
-  if (r0 >= Mr || c0 >= Nc) return;
-  const int al = r0 >> 1, be = c0 >> 1;
-  const double w = st.lam[(size_t)n * dc + al];
-  for (int ip = 0; ip < 2; ++ip)
-    for (int jp = 0; jp < 2; ++jp) {
-      zd v = zmk(0.0, 0.0);
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) v = zfma(Q[(ip * 2 + jp) * 4 + i * 2 + j], acc[i][j], v);
-      const size_t idx = (size_t)(jp * b + be) * ldc + (2 * al + ip);
-      C[idx] = v;
-      A[idx] = zscale(v, w);
-    }
+  double nrm = 0.0;
+  if (r0 < Mr && c0 < Nc) {
+    const int al = r0 >> 1, be = c0 >> 1;
+    const double w = st.lam[(size_t)n * dc + al];
+    for (int ip = 0; ip < 2; ++ip)
+      for (int jp = 0; jp < 2; ++jp) {
+        zd v = zmk(0.0, 0.0);
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) v = zfma(Q[(ip * 2 + jp) * 4 + i * 2 + j], acc[i][j], v);
+        const size_t idx = (size_t)(jp * b + be) * ldc + (2 * al + ip);
+        const zd wv = zscale(v, w);
+        C[idx] = v;
+        A[idx] = wv;
+        nrm += zabs2(wv);
+      }
+  }
+  nrm = block_sum256(nrm, red);
+  if (threadIdx.x == 0) nrm_part[part] = nrm;
 }
 
 // ----------------------------------------------------------------------------
@@ -119,6 +102,12 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
   const int TPP = 256 / W;         // threads per pair
   const int pr = t / TPP, lt = t % TPP;
   const double tol = s.tol;
+  // |gamma| below floor = 1e-28 |A|_F^2 means both columns are negligible (far
+  // below any kept Schmidt value): such pairs are left alone, which keeps wide
+  // matrices, whose surplus columns must shrink to zero, from sweeping forever.
+  double fro = 0.0;
+  for (int q = 0; q < s.nparts; ++q) fro += s.nrm_part[q];
+  const double floor_g = 1e-28 * fro;
   int sweep = 0;
   for (; sweep < s.max_sweeps; ++sweep) {
     if (t == 0) sh_rot = 0;
@@ -175,7 +164,7 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
           }
           const double ag = sqrt(fma(gr, gr, gi * gi));
           const double ab = al * be;
-          if (ab > 1e-300 && ag > tol * sqrt(ab)) {
+          if (ab > 1e-300 && ag > tol * sqrt(ab) && ag > floor_g) {
             const double zeta = (be - al) / (2.0 * ag);
             const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
             const double cs = 1.0 / sqrt(fma(tt, tt, 1.0));
@@ -339,7 +328,8 @@ hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, 
                        GateWork& w, hipStream_t stream) {
   const int dc = st.dcap;
   const int tiles = (2 * dc + ZT_M - 1) / ZT_M;
-  hipLaunchKernelGGL(k_contract, dim3(tiles, tiles), dim3(256), 0, stream, st, gt, g, theta, w.C, w.A, w.ldc);
+  hipLaunchKernelGGL(k_contract, dim3(tiles, tiles), dim3(256), 0, stream, st, gt, g, theta, w.C, w.A, w.ldc,
+                     w.nrm_part);
   SvdArgs s;
   s.A = w.A;
   s.lda = w.ldc;
@@ -358,6 +348,8 @@ hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, 
   s.dmax = w.dmax;
   s.tol = w.tol;
   s.max_sweeps = w.max_sweeps;
+  s.nrm_part = w.nrm_part;
+  s.nparts = tiles * tiles;
   const int W = svd_width(dc);
   const int P = (w.ncap + 2 * W - 1) / (2 * W);
   const size_t shm = (size_t)2 * W * (w.ldc + w.ldv) * sizeof(zd);

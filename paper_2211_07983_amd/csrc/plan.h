@@ -45,6 +45,7 @@ struct DevHamiltonian {
   int chunk = 1;
   std::vector<int> a_t, b_t;
   std::vector<uint64_t> xs, zs;
+  std::vector<double> coeff_h;
   std::vector<int64_t> order;
   std::vector<Chunk> chunks;
   DevBuf d_coeff, d_jobs, d_fin_slot, d_fin_term;
@@ -64,7 +65,7 @@ struct mps_ctx {
   int last_degen_grad = 0;
   GateWork gw{};
   SweepBuffers sb{};
-  DevBuf b_C, b_A, b_V, b_sv, b_perm, b_gmeta, b_gdmeta, b_rot, b_stats, b_theta;
+  DevBuf b_C, b_A, b_V, b_sv, b_perm, b_gmeta, b_gdmeta, b_rot, b_nrm, b_stats, b_stats2, b_theta;
   DevBuf b_Lid, b_Rid, b_Lslots, b_Y, b_Yid, b_energy, b_termval;
   ~mps_ctx();
   void set_device();
@@ -104,5 +105,6 @@ struct mps_plan {
   DevBuf tape;                     // per-gate records of one segment
   DevBuf work;                     // per-gate adjoint workspace
   DevBuf sweep_work;               // sweep-adjoint buffers
+  void* adj = nullptr;             // reverse-pass state (adjoint.hip)
   ~mps_plan();
 };

@@ -13,9 +13,12 @@
 #include "engine.h"
 #include "plan_impl.h"
 
+void plan_adj_free(void* a);
+
 mps_plan::~mps_plan() {
   delete state;
   delete replay;
+  plan_adj_free(adj);
 }
 
 mps_state* plan_new_state(mps_ctx* ctx, int N, const mps_trunc& tr, const uint8_t* occ) {

@@ -1,0 +1,101 @@
+"""GPU reverse pass (S7-S9) against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from vqe_inputs import configs
+from gpu_util import golden, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2211_07983_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def make_plan(ctx, p, g, **kw):
+    from paper_2211_07983_amd import Plan
+    return Plan(ctx, p.occ, g, p.n_qubits, p.ham_x, p.ham_z, p.ham_c, p.c0, p.bond_dim, p.eps, **kw)
+
+
+def grad_ok(g, ref, tol=1e-8):
+    d = np.abs(g - ref)
+    return (np.linalg.norm(g - ref) <= tol * np.linalg.norm(ref)
+            and d.max() <= tol * max(1.0, np.abs(ref).max()))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_energy_grad_matches_oracle(ctx, name):
+    p, g = configs.load(name)
+    gold = golden()[name]
+    plan = make_plan(ctx, p, g, ckpt_gates=256)
+    e, grad, st = plan.energy_grad(p.theta)
+    assert rel(e, gold["E"]) <= 1e-10
+    assert grad_ok(grad, np.array(gold["grad"]))
+    assert grad_ok(grad, np.array(gold["grad_exact"]), 1e-8)
+    plan.free()
+
+
+def test_checkpoint_interval_invariance(ctx):
+    p, g = configs.load("c1")
+    a = make_plan(ctx, p, g, ckpt_gates=7).energy_grad(p.theta)[1]
+    b = make_plan(ctx, p, g, ckpt_gates=5000).energy_grad(p.theta)[1]
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+
+
+def test_repeat_is_bitwise_deterministic(ctx):
+    p, g = configs.load("c1")
+    plan = make_plan(ctx, p, g)
+    e1, g1, _ = plan.energy_grad(p.theta)
+    e2, g2, _ = plan.energy_grad(p.theta)
+    assert e1 == e2 and np.array_equal(g1, g2)
+
+
+@pytest.mark.parametrize("seed", [1, 3])
+def test_truncating_gradient_matches_oracle(ctx, seed):
+    from oracle import mps
+    p, g = configs.small(8, 4, 6, seed=seed, theta_sigma=0.3)
+    E, grad, info = mps.energy_grad(p, g, p.theta)
+    assert max(info["discarded"]) > 1e-3
+    plan = make_plan(ctx, p, g)
+    e, gg, st = plan.energy_grad(p.theta)
+    assert rel(e, E) <= 1e-10
+    assert grad_ok(gg, grad)
+
+
+def test_energy_only_matches_energy_grad(ctx):
+    p, g = configs.load("c1")
+    plan = make_plan(ctx, p, g)
+    e1, _ = plan.energy(p.theta)
+    e2, _, _ = plan.energy_grad(p.theta)
+    assert e1 == e2
+
+
+def test_torch_autograd_function(ctx):
+    torch = pytest.importorskip("torch")
+    from paper_2211_07983_amd import EnergyGrad
+    p, g = configs.load("c1")
+    gold = golden()["c1"]
+    plan = make_plan(ctx, p, g)
+    th = torch.tensor(p.theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    E = EnergyGrad.apply(th, plan)
+    (3.0 * E).backward()
+    assert rel(E.item(), gold["E"]) <= 1e-10
+    assert grad_ok(th.grad.cpu().numpy() / 3.0, np.array(gold["grad"]))
+
+
+def test_gradient_validation_errors(ctx):
+    from paper_2211_07983_amd import MPSError
+    p, g = configs.load("c1")
+    plan = make_plan(ctx, p, g)
+    bad = p.theta.copy()
+    bad[0] = np.inf
+    with pytest.raises(MPSError) as ei:
+        plan.energy_grad(bad)
+    assert ei.value.code == -1
+    with pytest.raises(MPSError) as ei:
+        plan.energy_grad(p.theta[:-1])
+    assert ei.value.code == -1
