@@ -63,6 +63,13 @@ def load(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run paper_2211_07983_amd.build.build()")
+    # One HIP runtime per process: when PyTorch is installed its bundled
+    # libamdhip64.so.7 is loaded first and the library binds to the same one, so
+    # torch device pointers and streams are valid in both.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp = C.c_void_p
     lib.mps_ctx_create.argtypes = [C.c_int32, vp, C.POINTER(vp)]
