@@ -120,12 +120,22 @@ typedef struct {
   int32_t degenerate_cuts;      /* cuts with s_r - s_{r+1} < 1e-10 s_1         */
   double t_gates_ms, t_sweep_ms, t_backward_ms;
   int64_t n_gates_applied;
+  /* Sampled SVD launches of the forward pass (see mps_ctx_set_profiling):
+   * summed kernel time from HIP events around each sampled launch on the
+   * context's stream, and summed algorithmic work 84 p^3 (p = min(rows, cols)). */
+  double prof_svd_ms;
+  double prof_svd_flop;
+  int32_t prof_svd_launches;
+  int32_t prof_pad;
 } mps_stats;
 
 /* Context on HIP device `device` using `hip_stream` (a hipStream_t; NULL =
  * the null stream).  Returns MPS_EDEVICE if the device is not usable.       */
 mps_status mps_ctx_create(int32_t device, void* hip_stream, mps_ctx** out);
 void mps_ctx_destroy(mps_ctx* ctx);
+/* Bracket every `every`-th SVD launch of a forward pass with HIP events and
+ * report the sampled kernel time in mps_stats (0 = off, the default).       */
+mps_status mps_ctx_set_profiling(mps_ctx* ctx, int32_t every);
 /* Text of the last error on ctx; valid until the next call on ctx.          */
 const char* mps_last_error(const mps_ctx* ctx);
 

@@ -7,8 +7,10 @@ library.  There is no CPU fallback: if the library is missing, loading fails.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import sys
+import weakref
 
 import numpy as np
 
@@ -26,6 +28,26 @@ class MPSError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_abi.STATUS_NAMES.get(code, code)}: {msg}")
         self.code = code
+
+
+_live_children = weakref.WeakSet()    # states and plans
+_live_contexts = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    """Free every live handle before the interpreter (and the HIP runtime) shuts
+    down: states and plans first, then their contexts."""
+    for obj in list(_live_children):
+        try:
+            obj.free()
+        except Exception:
+            pass
+    for obj in list(_live_contexts):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def _ptr(a, ctype):
@@ -81,6 +103,10 @@ class Context:
             raise MPSError(st, "mps_ctx_create failed (no usable HIP device with cooperative launch)")
         self.h = h
         self.device = device
+        _live_contexts.add(self)
+
+    def set_profiling(self, every):
+        self.check(self._lib.mps_ctx_set_profiling(self.h, int(every)))
 
     def check(self, status):
         if status != 0:
@@ -88,6 +114,9 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for obj in list(_live_children):
+                if getattr(obj, "ctx", None) is self:
+                    obj.free()
             self._lib.mps_ctx_destroy(self.h)
             self.h = None
 
@@ -105,6 +134,7 @@ class State:
 
     def __init__(self, ctx, handle, n_qubits, d_max):
         self.ctx, self.h, self.n, self.d_max = ctx, handle, n_qubits, d_max
+        _live_children.add(self)
 
     @classmethod
     def product(cls, ctx, occ, d_max, eps, precision=0):
@@ -151,9 +181,9 @@ class State:
         return dims, tensors, lams
 
     def free(self):
-        if self.h:
+        if self.h and getattr(self.ctx, "h", None):
             self.ctx._lib.mps_state_free(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         if sys.is_finalizing():
@@ -180,6 +210,7 @@ class Plan:
                                            C.byref(tr), C.byref(go), C.byref(h)))
         self.h = h
         self.n_theta = int(np.max(gates.param)) + 1 if np.any(np.asarray(gates.kind) == 1) else 0
+        _live_children.add(self)
 
     def energy(self, theta):
         th = np.ascontiguousarray(theta, dtype=np.float64)
@@ -207,9 +238,9 @@ class Plan:
         return e.value, g, s.as_dict()
 
     def free(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             self.ctx._lib.mps_plan_free(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         if sys.is_finalizing():

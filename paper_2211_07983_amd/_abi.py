@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_EDEVIC
                 -4: "MPS_ENOCONV", -5: "MPS_EDEGEN"}
 
 EXPORTS = [
-    "mps_ctx_create", "mps_ctx_destroy", "mps_last_error", "mps_init_product",
+    "mps_ctx_create", "mps_ctx_destroy", "mps_ctx_set_profiling", "mps_last_error", "mps_init_product",
     "mps_apply_circuit", "mps_expect_paulisum", "mps_plan_create", "mps_energy_grad",
     "mps_plan_energy", "mps_state_export", "mps_state_size", "mps_state_qubits",
     "mps_state_free", "mps_plan_free",
@@ -47,7 +47,9 @@ class Stats(C.Structure):
                 ("max_bond", C.c_int32), ("gates_truncated", C.c_int32),
                 ("max_sweeps_used", C.c_int32), ("degenerate_cuts", C.c_int32),
                 ("t_gates_ms", C.c_double), ("t_sweep_ms", C.c_double),
-                ("t_backward_ms", C.c_double), ("n_gates_applied", C.c_int64)]
+                ("t_backward_ms", C.c_double), ("n_gates_applied", C.c_int64),
+                ("prof_svd_ms", C.c_double), ("prof_svd_flop", C.c_double),
+                ("prof_svd_launches", C.c_int32), ("prof_pad", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,6 +78,8 @@ def load(path=LIB_PATH):
     lib.mps_ctx_create.restype = C.c_int32
     lib.mps_ctx_destroy.argtypes = [vp]
     lib.mps_ctx_destroy.restype = None
+    lib.mps_ctx_set_profiling.argtypes = [vp, C.c_int32]
+    lib.mps_ctx_set_profiling.restype = C.c_int32
     lib.mps_last_error.argtypes = [vp]
     lib.mps_last_error.restype = C.c_char_p
     lib.mps_init_product.argtypes = [vp, C.c_int32, C.POINTER(C.c_uint8), C.POINTER(Trunc), C.POINTER(vp)]

@@ -102,6 +102,10 @@ __device__ inline void gate_matrix(const GateTable& gt, int g, const double* the
 int svd_width(int dcap);
 hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, const double* theta,
                        GateWork& w, hipStream_t stream);
+hipError_t launch_contract(const MpsView& st, const GateTable& gt, int g, const double* theta, GateWork& w,
+                           hipStream_t stream);
+hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stream);
+hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t stream);
 hipError_t svd_set_attributes(int dcap, size_t shm);
 
 // ----------------------------------------------------------------------------

@@ -40,7 +40,9 @@ void* DevBuf::ensure(size_t n) {
 // ----------------------------------------------------------------------------
 // context
 // ----------------------------------------------------------------------------
-mps_ctx::~mps_ctx() {}
+mps_ctx::~mps_ctx() {
+  for (hipEvent_t ev : prof_ev) (void)hipEventDestroy(ev);
+}
 
 void mps_ctx::set_device() { HIPCHK(hipSetDevice(device)); }
 
@@ -288,13 +290,62 @@ void run_energy(mps_state* st, DevHamiltonian& H) {
   HIPCHK(launch_energy_sum(v, ctx->sb, H.d_coeff_ptr, H.K, H.c0, s));
 }
 
+static const int kMaxProfSamples = 8192;
+
 void run_gates(mps_state* st, DevCircuit& C, const double* theta_dev, int g0, int g1) {
   mps_ctx* ctx = st->ctx;
   MpsView v = view_of(st);
-  for (int g = g0; g < g1; ++g) HIPCHK(launch_gate(v, C.tab, g, C.bond_h[g], theta_dev, ctx->gw, ctx->stream));
+  hipStream_t s = ctx->stream;
+  for (int g = g0; g < g1; ++g) {
+    const int k = (int)ctx->prof_n.size();
+    if (ctx->prof_every > 0 && g % ctx->prof_every == 0 && k < kMaxProfSamples) {
+      if ((int)ctx->prof_ev.size() < 2 * (k + 1)) {
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        ctx->prof_ev.push_back(a);
+        ctx->prof_ev.push_back(b);
+      }
+      int* slots = (int*)ctx->b_prof.ensure((size_t)kMaxProfSamples * 4 * sizeof(int));
+      HIPCHK(launch_contract(v, C.tab, g, theta_dev, ctx->gw, s));
+      HIPCHK(hipEventRecord(ctx->prof_ev[2 * k], s));
+      HIPCHK(launch_svd(v, C.bond_h[g], ctx->gw, s));
+      HIPCHK(hipEventRecord(ctx->prof_ev[2 * k + 1], s));
+      HIPCHK(hipMemcpyAsync(slots + 4 * k, ctx->gw.gmeta + 8, 3 * sizeof(int), hipMemcpyDeviceToDevice, s));
+      HIPCHK(launch_update(v, C.bond_h[g], ctx->gw, s));
+      ctx->prof_n.push_back(g);
+    } else {
+      HIPCHK(launch_gate(v, C.tab, g, C.bond_h[g], theta_dev, ctx->gw, s));
+    }
+  }
+}
+
+// Sums the sampled SVD launches of this call into stats (synchronises).
+static void collect_profile(mps_ctx* ctx, mps_stats* out) {
+  const int k = (int)ctx->prof_n.size();
+  double ms = 0.0, flop = 0.0;
+  if (k > 0) {
+    std::vector<int> meta((size_t)4 * k);
+    HIPCHK(hipMemcpyAsync(meta.data(), ctx->b_prof.p, meta.size() * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < k; ++q) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, ctx->prof_ev[2 * q], ctx->prof_ev[2 * q + 1]));
+      ms += t;
+      const double p = std::min(meta[4 * q], meta[4 * q + 1]);
+      flop += 84.0 * p * p * p;
+    }
+  }
+  if (out) {
+    out->prof_svd_ms = ms;
+    out->prof_svd_flop = flop;
+    out->prof_svd_launches = k;
+  }
+  ctx->prof_n.clear();
 }
 
 void read_stats(mps_ctx* ctx, mps_stats* out, int64_t gates) {
+  collect_profile(ctx, out);
   GateStats gs;
   HIPCHK(hipMemcpyAsync(&gs, ctx->gw.stats, sizeof(GateStats), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -341,6 +392,12 @@ void mps_ctx_destroy(mps_ctx* ctx) {
 }
 
 const char* mps_last_error(const mps_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mps_status mps_ctx_set_profiling(mps_ctx* ctx, int32_t every) {
+  if (!ctx || every < 0) return MPS_EINVAL;
+  ctx->prof_every = every;
+  return MPS_OK;
+}
 
 mps_status mps_init_product(mps_ctx* ctx, int32_t n_qubits, const uint8_t* occ_bits, const mps_trunc* trunc,
                             mps_state** out) {

@@ -255,6 +255,9 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
     }
     const double nu = sqrt(kept);
     s.gmeta[0] = r;
+    s.gmeta[8] = M;
+    s.gmeta[9] = ncol;
+    s.gmeta[10] = used;
     s.gdmeta[0] = nu;
     const double disc = tot > 0.0 ? (tot - kept) / tot : 0.0;
     GateStats* gs = s.stats;
@@ -324,12 +327,7 @@ __global__ __launch_bounds__(256) void k_update_right(MpsView st, int n, const z
 // ----------------------------------------------------------------------------
 int svd_width(int dcap) { return dcap <= 128 ? 8 : 4; }
 
-hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, const double* theta,
-                       GateWork& w, hipStream_t stream) {
-  const int dc = st.dcap;
-  const int tiles = (2 * dc + ZT_M - 1) / ZT_M;
-  hipLaunchKernelGGL(k_contract, dim3(tiles, tiles), dim3(256), 0, stream, st, gt, g, theta, w.C, w.A, w.ldc,
-                     w.nrm_part);
+static SvdArgs svd_args(const MpsView& st, int bond, GateWork& w) {
   SvdArgs s;
   s.A = w.A;
   s.lda = w.ldc;
@@ -342,15 +340,29 @@ hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, 
   s.gmeta = w.gmeta;
   s.gdmeta = w.gdmeta;
   s.rotflag = w.rotflag;
-  s.lam_out = st.lam + (size_t)(bond + 1) * dc;
+  s.lam_out = st.lam + (size_t)(bond + 1) * st.dcap;
   s.stats = w.stats;
   s.eps = w.eps;
   s.dmax = w.dmax;
   s.tol = w.tol;
   s.max_sweeps = w.max_sweeps;
   s.nrm_part = w.nrm_part;
+  const int tiles = (2 * st.dcap + ZT_M - 1) / ZT_M;
   s.nparts = tiles * tiles;
-  const int W = svd_width(dc);
+  return s;
+}
+
+hipError_t launch_contract(const MpsView& st, const GateTable& gt, int g, const double* theta, GateWork& w,
+                           hipStream_t stream) {
+  const int tiles = (2 * st.dcap + ZT_M - 1) / ZT_M;
+  hipLaunchKernelGGL(k_contract, dim3(tiles, tiles), dim3(256), 0, stream, st, gt, g, theta, w.C, w.A, w.ldc,
+                     w.nrm_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stream) {
+  SvdArgs s = svd_args(st, bond, w);
+  const int W = svd_width(st.dcap);
   const int P = (w.ncap + 2 * W - 1) / (2 * W);
   const size_t shm = (size_t)2 * W * (w.ldc + w.ldv) * sizeof(zd);
   void* args[] = {&s};
@@ -360,13 +372,26 @@ hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, 
     e = hipLaunchCooperativeKernel((const void*)k_svd_jacobi<8>, dim3(P), dim3(256), args, shm, stream);
   else
     e = hipLaunchCooperativeKernel((const void*)k_svd_jacobi<4>, dim3(P), dim3(256), args, shm, stream);
-  if (e != hipSuccess) return e;
+  return e;
+}
+
+hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t stream) {
+  const int dc = st.dcap;
   const int tm = (2 * dc + ZT_M - 1) / ZT_M, tn = (dc + ZT_N - 1) / ZT_N;
   hipLaunchKernelGGL(k_update_left, dim3(tn, tm), dim3(256), 0, stream, st, bond, (const zd*)w.C, w.ldc,
                      (const zd*)w.V, w.ldv, (const int*)w.perm, (const int*)w.gmeta, (const double*)w.gdmeta);
   hipLaunchKernelGGL(k_update_right, dim3(dc), dim3(256), 0, stream, st, bond, (const zd*)w.V, w.ldv,
                      (const int*)w.perm, (const int*)w.gmeta);
   return hipGetLastError();
+}
+
+hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, const double* theta,
+                       GateWork& w, hipStream_t stream) {
+  hipError_t e = launch_contract(st, gt, g, theta, w, stream);
+  if (e != hipSuccess) return e;
+  e = launch_svd(st, bond, w, stream);
+  if (e != hipSuccess) return e;
+  return launch_update(st, bond, w, stream);
 }
 
 hipError_t svd_set_attributes(int dcap, size_t shm) {
