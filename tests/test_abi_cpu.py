@@ -12,7 +12,8 @@ LIB = os.path.join(ROOT, "paper_2211_07983_amd", "libmpsvqe.so")
 
 def declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(mps_[a-z_]+)\s*\(", text)))
+    decl = r"^\s*(?:mps_status|void|const char\s*\*|int64_t|int32_t)\s+(mps_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
 
 
 def test_header_declares_the_four_operations():
