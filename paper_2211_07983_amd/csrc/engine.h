@@ -42,9 +42,11 @@ struct GateWork {
   double* gdmeta; // [4]
   int* rotflag;   // [128]
   double* nrm_part; // [256] per-tile |A|^2 partial sums of k_contract
+  double* cnorm;    // [ncap] column norms of the Jacobi sweeps
   GateStats* stats;
   int ldc, ldv, ncap;
   double eps, tol;
+  double defl;      // convergence vote ignores columns with |a|^2 <= defl |A|_F^2
   int dmax, max_sweeps;
 };
 
@@ -68,6 +70,9 @@ struct SvdArgs {
   int max_sweeps;
   const double* nrm_part;
   int nparts;
+  int trans;         // 1: the matrix is C~^H (columns = rows of C~)
+  double defl;       // columns with |a|^2 <= defl |A|_F^2 do not count for convergence
+  double* cnorm;     // [ncap] squared column norms at the end of each sweep
 };
 
 // ----------------------------------------------------------------------------
@@ -99,13 +104,19 @@ __device__ inline void gate_matrix(const GateTable& gt, int g, const double* the
 }
 
 
+// GATE_TAPE: Jacobi on C~ with the right rotations accumulated in V (the full
+// decomposition the reverse pass needs).  GATE_FWD: Jacobi on C~^H without
+// accumulation; the normalised columns are the right singular vectors.
+enum GateMode { GATE_TAPE = 0, GATE_FWD = 1 };
+
 int svd_width(int dcap);
 hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, const double* theta,
-                       GateWork& w, hipStream_t stream);
+                       GateWork& w, hipStream_t stream, GateMode mode = GATE_TAPE);
 hipError_t launch_contract(const MpsView& st, const GateTable& gt, int g, const double* theta, GateWork& w,
-                           hipStream_t stream);
-hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stream);
-hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t stream);
+                           hipStream_t stream, GateMode mode = GATE_TAPE);
+hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stream, GateMode mode = GATE_TAPE);
+hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t stream, GateMode mode = GATE_TAPE);
+size_t svd_shared_bytes(int dcap, int ldc, int ldv, GateMode mode);
 hipError_t svd_set_attributes(int dcap, size_t shm);
 
 // ----------------------------------------------------------------------------

@@ -63,12 +63,17 @@ void mps_ctx::ensure_gate_work(int dcap, const mps_trunc& tr, int max_sweeps) {
   gw.gdmeta = (double*)b_gdmeta.ensure(16 * sizeof(double));
   gw.rotflag = (int*)b_rot.ensure(128 * sizeof(int));
   gw.nrm_part = (double*)b_nrm.ensure(256 * sizeof(double));
+  gw.cnorm = (double*)b_cnorm.ensure((size_t)ncap * sizeof(double));
   gw.stats = (GateStats*)b_stats.ensure(sizeof(GateStats));
   gw.eps = tr.eps;
   gw.dmax = tr.d_max;
   gw.max_sweeps = std::min(std::max(max_sweeps, 1), 100);   // per-sweep counters: 128 slots
   gw.tol = std::max(1e-15, 8.0 * std::sqrt((double)ldc) * 2.220446049250313e-16);
-  const size_t shm = (size_t)2 * W * (ldc + ncap) * sizeof(zd);
+  // Columns below 1e-2 eps in norm are discarded whatever their final value;
+  // once only rotations that cannot move the other columns remain, the kept
+  // part has converged.
+  gw.defl = (1e-2 * tr.eps) * (1e-2 * tr.eps);
+  const size_t shm = svd_shared_bytes(dcap, ldc, ncap, GATE_TAPE);
   if (shm > shm_set) {
     HIPCHK(svd_set_attributes(dcap, shm));
     shm_set = shm;
@@ -292,7 +297,7 @@ void run_energy(mps_state* st, DevHamiltonian& H) {
 
 static const int kMaxProfSamples = 8192;
 
-void run_gates(mps_state* st, DevCircuit& C, const double* theta_dev, int g0, int g1) {
+void run_gates(mps_state* st, DevCircuit& C, const double* theta_dev, int g0, int g1, GateMode mode) {
   mps_ctx* ctx = st->ctx;
   MpsView v = view_of(st);
   hipStream_t s = ctx->stream;
@@ -307,15 +312,15 @@ void run_gates(mps_state* st, DevCircuit& C, const double* theta_dev, int g0, in
         ctx->prof_ev.push_back(b);
       }
       int* slots = (int*)ctx->b_prof.ensure((size_t)kMaxProfSamples * 4 * sizeof(int));
-      HIPCHK(launch_contract(v, C.tab, g, theta_dev, ctx->gw, s));
+      HIPCHK(launch_contract(v, C.tab, g, theta_dev, ctx->gw, s, mode));
       HIPCHK(hipEventRecord(ctx->prof_ev[2 * k], s));
-      HIPCHK(launch_svd(v, C.bond_h[g], ctx->gw, s));
+      HIPCHK(launch_svd(v, C.bond_h[g], ctx->gw, s, mode));
       HIPCHK(hipEventRecord(ctx->prof_ev[2 * k + 1], s));
       HIPCHK(hipMemcpyAsync(slots + 4 * k, ctx->gw.gmeta + 8, 3 * sizeof(int), hipMemcpyDeviceToDevice, s));
-      HIPCHK(launch_update(v, C.bond_h[g], ctx->gw, s));
+      HIPCHK(launch_update(v, C.bond_h[g], ctx->gw, s, mode));
       ctx->prof_n.push_back(g);
     } else {
-      HIPCHK(launch_gate(v, C.tab, g, C.bond_h[g], theta_dev, ctx->gw, s));
+      HIPCHK(launch_gate(v, C.tab, g, C.bond_h[g], theta_dev, ctx->gw, s, mode));
     }
   }
 }
@@ -444,7 +449,7 @@ mps_status mps_apply_circuit(mps_state* st, const mps_circuit* circuit, const do
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
-    run_gates(st, C, th, 0, C.G);
+    run_gates(st, C, th, 0, C.G, GATE_FWD);
     HIPCHK(hipEventRecord(e1, s));
     read_stats(ctx, stats, C.G);
     float ms = 0.f;

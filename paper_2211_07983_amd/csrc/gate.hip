@@ -14,14 +14,17 @@ namespace cg = cooperative_groups;
 
 // ----------------------------------------------------------------------------
 // k_contract: C[(a,i'),(j',b)] = sum_{ij} Q[(i'j'),(ij)] sum_g B_n[a,i,g] B_{n+1}[g,j,b]
-// and A = lambda_{n-1}[a] C.  GEMM rows r = 2a + i, columns c = 2b + j so that
+// and A = lambda_{n-1}[a] C (trans = 0) or A = (lambda_{n-1} C)^H (trans = 1).  GEMM rows r = 2a + i, columns c = 2b + j so that
 // each thread holds the four (i, j) values of one (alpha, beta) pair.
 // C and A are column-major with leading dimension ldc; column index j'*b + beta.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int g, const double* theta,
-                                                  zd* C, zd* A, int ldc, double* nrm_part) {
+                                                  zd* C, zd* A, int ldc, double* nrm_part, int trans,
+                                                  int* rotflag) {
   __shared__ zd Q[16];
   __shared__ double red[256];
+  // the Jacobi kernel that follows counts rotations per sweep in rotflag
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 128) rotflag[threadIdx.x] = 0;
   const int n = gt.bond[g];
   const int a = st.dims[n], m = st.dims[n + 1], b = st.dims[n + 2];
   const int Mr = 2 * a, Nc = 2 * b;
@@ -53,7 +56,10 @@ __global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int 
         const size_t idx = (size_t)(jp * b + be) * ldc + (2 * al + ip);
         const zd wv = zscale(v, w);
         C[idx] = v;
-        A[idx] = wv;
+        if (trans)
+          A[(size_t)(2 * al + ip) * ldc + (jp * b + be)] = zconj(wv);
+        else
+          A[idx] = wv;
         nrm += zabs2(wv);
       }
   }
@@ -83,23 +89,163 @@ __device__ inline void tourney(int P, int k, int p, int& q0, int& q1) {
   }
 }
 
-template <int W>
+// Cross-lane sums over groups of TPP consecutive lanes.  Every step pairs
+// lanes symmetrically (l <-> l^1, l^2, the two halves of 8, of 16, of 32), so
+// all lanes of a group end with bitwise identical totals and therefore take
+// identical rotation decisions.
+template <int CTRL>
+__device__ inline double dpp_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return v + __hiloint2double(hi, lo);
+}
+__device__ inline double swz16_add(double v) {   // lane l <-> l ^ 16
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+  return v + __hiloint2double(hi, lo);
+}
+template <int TPP>
+__device__ inline void group_sum4(double& a, double& b, double& c, double& d) {
+  static_assert(TPP == 16 || TPP == 32 || TPP == 64, "group size");
+  a = dpp_add<0xB1>(a); b = dpp_add<0xB1>(b); c = dpp_add<0xB1>(c); d = dpp_add<0xB1>(d);      // quad [1,0,3,2]
+  a = dpp_add<0x4E>(a); b = dpp_add<0x4E>(b); c = dpp_add<0x4E>(c); d = dpp_add<0x4E>(d);      // quad [2,3,0,1]
+  a = dpp_add<0x141>(a); b = dpp_add<0x141>(b); c = dpp_add<0x141>(c); d = dpp_add<0x141>(d);  // half-row mirror
+  a = dpp_add<0x140>(a); b = dpp_add<0x140>(b); c = dpp_add<0x140>(c); d = dpp_add<0x140>(d);  // row mirror
+  if (TPP >= 32) {
+    a = swz16_add(a); b = swz16_add(b); c = swz16_add(c); d = swz16_add(d);
+  }
+  if (TPP == 64) {
+    a += __shfl_xor(a, 32); b += __shfl_xor(b, 32); c += __shfl_xor(c, 32); d += __shfl_xor(d, 32);
+  }
+}
+
+// Rotation of the column pair (x, y): alpha = |x|^2, beta = |y|^2,
+// gamma = x^H y = |gamma| e^{i phi}.  With d = beta - alpha and
+// h = 2 sign(d) / (|d| + sqrt(d^2 + 4 |gamma|^2)) the tangent of the angle is
+// t = h |gamma| and c = 1 / sqrt(1 + t^2); the unitary update
+//   x' = c x - c h conj(gamma) y,    y' = c h gamma x + c y
+// makes x'^H y' = 0.  Returns false when the pair is already orthogonal
+// (|gamma| <= tol sqrt(alpha beta)) or negligible (|gamma| <= floor_g).
+// `sig` tells whether the rotation can still change a column that matters:
+// one of the two columns is above the deflation level and either both are or
+// the relative change of the larger one exceeds tol.
+__device__ inline bool jacobi_rotation(double al, double be, double gr, double gi, double tol, double floor_g,
+                                       double dl, double& c, zd& p, zd& q, bool& sig) {
+  const double g2 = fma(gr, gr, gi * gi);
+  const double ab = al * be;
+  if (!(ab > 1e-300) || g2 <= tol * tol * ab || g2 <= floor_g * floor_g) return false;
+  const double d = be - al;
+  const double qd = sqrt(fma(d, d, 4.0 * g2));
+  const double h = (d >= 0.0 ? 2.0 : -2.0) / (fabs(d) + qd);
+  c = 1.0 / sqrt(fma(h * h, g2, 1.0));
+  const double ch = c * h;
+  p = zmk(ch * gr, -ch * gi);    // c h conj(gamma)
+  q = zmk(ch * gr, ch * gi);     // c h gamma
+  const double mn = fmin(al, be), mx = fmax(al, be);
+  sig = mx > dl && (mn > dl || g2 * mn > tol * tol * mx * mx * mx);
+  return true;
+}
+
+// partial sums of |u|^2, |v|^2 and conj(u) v
+__device__ inline void pair_acc(const zd u, const zd v, double& al, double& be, double& gr, double& gi) {
+  al = fma(u.x, u.x, fma(u.y, u.y, al));
+  be = fma(v.x, v.x, fma(v.y, v.y, be));
+  gr = fma(u.x, v.x, fma(u.y, v.y, gr));
+  gi = fma(u.x, v.y, fma(-u.y, v.x, gi));
+}
+
+__device__ inline zd rot_x(const zd u, const zd v, double c, const zd p) { return zsub(zscale(u, c), zmul(p, v)); }
+__device__ inline zd rot_y(const zd u, const zd v, double c, const zd q) { return zadd(zmul(q, u), zscale(v, c)); }
+
+// Loads the two column blocks (q0, q1) of a (and of v when ACC) into LDS with
+// eight independent loads in flight per thread.
+__device__ inline void load_blocks(zd* dst, int ldst, const zd* src, int lds, int rows, int ncol, int W, int q0,
+                                   int q1, bool identity) {
+  const int tot = 2 * W * rows;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * 256) {
+    zd buf[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256;
+      if (e < tot) {
+        const int c = e / rows, r = e - c * rows;
+        const int gc = (c < W ? q0 : q1) * W + (c % W);
+        buf[u] = identity ? zmk(r == gc ? 1.0 : 0.0, 0.0) : (gc < ncol ? src[(size_t)gc * lds + r] : zmk(0.0, 0.0));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256;
+      if (e < tot) {
+        const int c = e / rows, r = e - c * rows;
+        dst[c * ldst + r] = buf[u];
+      }
+    }
+  }
+}
+
+__device__ inline void store_blocks(zd* dst, int ldd, const zd* src, int lsrc, int rows, int ncol, int W, int q0,
+                                    int q1) {
+  for (int e = threadIdx.x; e < 2 * W * rows; e += 256) {
+    const int c = e / rows, r = e - c * rows;
+    const int gc = (c < W ? q0 : q1) * W + (c % W);
+    if (gc < ncol) dst[(size_t)gc * ldd + r] = src[c * lsrc + r];
+  }
+}
+
+// Deflation level for the next sweep's convergence vote.  From the squared
+// column norms cn at the end of a sweep: r = min(dmax, #{cn > eps^2}) >= 1
+// columns would be kept and kappa is the r-th largest norm.  Pairs whose two
+// columns both lie below 1e-2 kappa (ten times below the cut in singular
+// value) can neither enter the kept set nor move it, so once only such
+// rotations remain the kept part has converged.  Every work-group evaluates
+// this on the same data and reaches the same value.
+__device__ inline double keep_level(const double* cn, int ncol, int dmax, double eps, double base, double* kn,
+                                    int* shcnt, double* shkap) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    *shcnt = 0;
+    *shkap = 0.0;
+  }
+  for (int c = t; c < ncol; c += 256) kn[c] = cn[c];
+  __syncthreads();
+  int cnt = 0;
+  for (int c = t; c < ncol; c += 256) cnt += kn[c] > eps * eps;
+  if (cnt) atomicAdd(shcnt, cnt);
+  __syncthreads();
+  int r = *shcnt < dmax ? *shcnt : dmax;
+  if (r < 1) r = 1;
+  for (int c = t; c < ncol; c += 256) {
+    const double v = kn[c];
+    int rank = 0;
+    for (int q = 0; q < ncol; ++q) {
+      const double u = kn[q];
+      rank += (u > v) || (u == v && q < c);
+    }
+    if (rank == r - 1) *shkap = v;
+  }
+  __syncthreads();
+  return fmax(1e-2 * *shkap, base);
+}
+
+template <int W, bool ACC>
 __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
+  constexpr int TPP = 256 / W;     // threads per column pair
+  constexpr int RPT = 8;           // rows per thread held in registers (M, ncol <= 8 * TPP)
   cg::grid_group grid = cg::this_grid();
   extern __shared__ zd lds[];
   const int n = s.bond;
   const int a = s.dims[n], b = s.dims[n + 2];
-  const int M = 2 * a, ncol = 2 * b;
+  const int M = s.trans ? 2 * b : 2 * a, ncol = s.trans ? 2 * a : 2 * b;
   const int P = (ncol + 2 * W - 1) / (2 * W);
   const int p = blockIdx.x;
   const int t = threadIdx.x;
   const int mpad = s.lda;          // LDS column stride for A
   const int vpad = s.ldv;          // LDS column stride for V
   zd* Al = lds;                    // [2W][mpad]
-  zd* Vl = lds + 2 * W * mpad;     // [2W][vpad]
+  zd* Vl = lds + 2 * W * mpad;     // [2W][vpad] (ACC only)
   __shared__ int sh_rot;
   __shared__ int sh_stop;
-  const int TPP = 256 / W;         // threads per pair
   const int pr = t / TPP, lt = t % TPP;
   const double tol = s.tol;
   // |gamma| below floor = 1e-28 |A|_F^2 means both columns are negligible (far
@@ -108,6 +254,10 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
   double fro = 0.0;
   for (int q = 0; q < s.nparts; ++q) fro += s.nrm_part[q];
   const double floor_g = 1e-28 * fro;
+  double dl = s.defl * fro;
+  __shared__ double kn[512];
+  __shared__ int shcnt;
+  __shared__ double shkap;
   int sweep = 0;
   for (; sweep < s.max_sweeps; ++sweep) {
     if (t == 0) sh_rot = 0;
@@ -115,26 +265,15 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
       int q0, q1;
       tourney(P, k, p, q0, q1);
       if (p < P) {
-        // load both blocks (columns >= ncol are zero padding, V = I there)
-        for (int c = 0; c < 2 * W; ++c) {
-          const int gc = (c < W ? q0 : q1) * W + (c % W);
-          for (int r = t; r < M; r += 256)
-            Al[c * mpad + r] = gc < ncol ? s.A[(size_t)gc * s.lda + r] : zmk(0.0, 0.0);
-          for (int r = t; r < ncol; r += 256) {
-            zd v;
-            if (sweep == 0 && k == 0)
-              v = zmk(r == gc ? 1.0 : 0.0, 0.0);
-            else
-              v = gc < ncol ? s.V[(size_t)gc * s.ldv + r] : zmk(0.0, 0.0);
-            Vl[c * vpad + r] = v;
-          }
-        }
+        load_blocks(Al, mpad, s.A, s.lda, M, ncol, W, q0, q1, false);
+        if (ACC) load_blocks(Vl, vpad, s.V, s.ldv, ncol, ncol, W, q0, q1, sweep == 0 && k == 0);
         __syncthreads();
-        const int nsub = (k == 0) ? (2 * W - 1) : W;
-        for (int sub = 0; sub < nsub; ++sub) {
-          int c0, c1;
-          if (k == 0) {
+        bool rot = false;
+        if (k == 0) {
+          // all pairs of the 2W columns, circle ordering
+          for (int sub = 0; sub < 2 * W - 1; ++sub) {
             const int R = 2 * W - 1;
+            int c0, c1;
             if (pr == 0) {
               c0 = R;
               c1 = sub % R;
@@ -142,74 +281,127 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
               c0 = (sub + pr) % R;
               c1 = (sub - pr + R) % R;
             }
-          } else {
-            c0 = pr;
-            c1 = W + (pr + sub) % W;
-          }
-          zd* x = Al + c0 * mpad;
-          zd* y = Al + c1 * mpad;
-          double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-          for (int r = lt; r < M; r += TPP) {
-            const zd u = x[r], v = y[r];
-            al = fma(u.x, u.x, fma(u.y, u.y, al));
-            be = fma(v.x, v.x, fma(v.y, v.y, be));
-            gr = fma(u.x, v.x, fma(u.y, v.y, gr));
-            gi = fma(u.x, v.y, fma(-u.y, v.x, gi));
-          }
-          for (int o = TPP / 2; o > 0; o >>= 1) {
-            al += __shfl_xor(al, o, TPP);
-            be += __shfl_xor(be, o, TPP);
-            gr += __shfl_xor(gr, o, TPP);
-            gi += __shfl_xor(gi, o, TPP);
-          }
-          const double ag = sqrt(fma(gr, gr, gi * gi));
-          const double ab = al * be;
-          if (ab > 1e-300 && ag > tol * sqrt(ab) && ag > floor_g) {
-            const double zeta = (be - al) / (2.0 * ag);
-            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-            const double cs = 1.0 / sqrt(fma(tt, tt, 1.0));
-            const double sn = cs * tt;
-            // e^{-i phi} with gamma = |gamma| e^{i phi}
-            const zd em = zmk(gr / ag, -gi / ag);
-            const zd sem = zscale(em, sn), cem = zscale(em, cs);
-            for (int r = lt; r < M; r += TPP) {
-              const zd u = x[r], v = y[r];
-              x[r] = zsub(zscale(u, cs), zmul(sem, v));
-              y[r] = zadd(zscale(u, sn), zmul(cem, v));
+            zd* x = Al + c0 * mpad;
+            zd* y = Al + c1 * mpad;
+            double al0 = 0.0, be0 = 0.0, gr0 = 0.0, gi0 = 0.0, al1 = 0.0, be1 = 0.0, gr1 = 0.0, gi1 = 0.0;
+            int r = lt;
+            for (; r + TPP < M; r += 2 * TPP) {
+              pair_acc(x[r], y[r], al0, be0, gr0, gi0);
+              pair_acc(x[r + TPP], y[r + TPP], al1, be1, gr1, gi1);
             }
-            zd* xv = Vl + c0 * vpad;
-            zd* yv = Vl + c1 * vpad;
-            for (int r = lt; r < ncol; r += TPP) {
-              const zd u = xv[r], v = yv[r];
-              xv[r] = zsub(zscale(u, cs), zmul(sem, v));
-              yv[r] = zadd(zscale(u, sn), zmul(cem, v));
+            if (r < M) pair_acc(x[r], y[r], al0, be0, gr0, gi0);
+            double al = al0 + al1, be = be0 + be1, gr = gr0 + gr1, gi = gi0 + gi1;
+            group_sum4<TPP>(al, be, gr, gi);
+            double c;
+            zd pp, qq;
+            bool sig;
+            if (jacobi_rotation(al, be, gr, gi, tol, floor_g, dl, c, pp, qq, sig)) {
+              for (int rr = lt; rr < M; rr += TPP) {
+                const zd u = x[rr], v = y[rr];
+                x[rr] = rot_x(u, v, c, pp);
+                y[rr] = rot_y(u, v, c, qq);
+              }
+              if (ACC) {
+                zd* xv = Vl + c0 * vpad;
+                zd* yv = Vl + c1 * vpad;
+                for (int rr = lt; rr < ncol; rr += TPP) {
+                  const zd u = xv[rr], v = yv[rr];
+                  xv[rr] = rot_x(u, v, c, pp);
+                  yv[rr] = rot_y(u, v, c, qq);
+                }
+              }
+              rot |= sig;
             }
-            if (lt == 0) sh_rot = 1;
+            __syncthreads();
+          }
+        } else {
+          // cross pairs: column pr of the first block stays in registers
+          const int c0 = pr;
+          zd xr[RPT], xv[RPT];
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const int r = lt + i * TPP;
+            xr[i] = r < M ? Al[c0 * mpad + r] : zmk(0.0, 0.0);
+            if (ACC) xv[i] = r < ncol ? Vl[c0 * vpad + r] : zmk(0.0, 0.0);
+          }
+          for (int sub = 0; sub < W; ++sub) {
+            const int c1 = W + (pr + sub) % W;
+            zd* y = Al + c1 * mpad;
+            zd yr[RPT];
+            double al0 = 0.0, be0 = 0.0, gr0 = 0.0, gi0 = 0.0, al1 = 0.0, be1 = 0.0, gr1 = 0.0, gi1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPT; i += 2) {
+              const int r0 = lt + i * TPP, r1 = r0 + TPP;
+              yr[i] = r0 < M ? y[r0] : zmk(0.0, 0.0);
+              yr[i + 1] = r1 < M ? y[r1] : zmk(0.0, 0.0);
+              pair_acc(xr[i], yr[i], al0, be0, gr0, gi0);
+              pair_acc(xr[i + 1], yr[i + 1], al1, be1, gr1, gi1);
+            }
+            double al = al0 + al1, be = be0 + be1, gr = gr0 + gr1, gi = gi0 + gi1;
+            group_sum4<TPP>(al, be, gr, gi);
+            double c;
+            zd pp, qq;
+            bool sig;
+            if (jacobi_rotation(al, be, gr, gi, tol, floor_g, dl, c, pp, qq, sig)) {
+#pragma unroll
+              for (int i = 0; i < RPT; ++i) {
+                const int r = lt + i * TPP;
+                const zd u = xr[i], v = yr[i];
+                xr[i] = rot_x(u, v, c, pp);
+                if (r < M) y[r] = rot_y(u, v, c, qq);
+              }
+              if (ACC) {
+                zd* yv = Vl + c1 * vpad;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                  const int r = lt + i * TPP;
+                  if (r < ncol) {
+                    const zd u = xv[i], v = yv[r];
+                    xv[i] = rot_x(u, v, c, pp);
+                    yv[r] = rot_y(u, v, c, qq);
+                  }
+                }
+              }
+              rot |= sig;
+            }
+            __syncthreads();
+          }
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const int r = lt + i * TPP;
+            if (r < M) Al[c0 * mpad + r] = xr[i];
+            if (ACC && r < ncol) Vl[c0 * vpad + r] = xv[i];
           }
           __syncthreads();
         }
-        for (int c = 0; c < 2 * W; ++c) {
-          const int gc = (c < W ? q0 : q1) * W + (c % W);
-          if (gc >= ncol) continue;
-          for (int r = t; r < M; r += 256) s.A[(size_t)gc * s.lda + r] = Al[c * mpad + r];
-          for (int r = t; r < ncol; r += 256) s.V[(size_t)gc * s.ldv + r] = Vl[c * vpad + r];
+        if (rot && lt == 0) sh_rot = 1;
+        if (k == 2 * P - 2) {
+          // squared norms of the 2W columns after the sweep's last round
+          for (int c = pr; c < 2 * W; c += W) {
+            double acc = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+            for (int r = lt; r < M; r += TPP) acc += zabs2(Al[c * mpad + r]);
+            group_sum4<TPP>(acc, d1, d2, d3);
+            const int gc = (c < W ? q0 : q1) * W + (c % W);
+            if (lt == 0 && gc < ncol) s.cnorm[gc] = acc;
+          }
         }
+        store_blocks(s.A, s.lda, Al, mpad, M, ncol, W, q0, q1);
+        if (ACC) store_blocks(s.V, s.ldv, Vl, vpad, ncol, ncol, W, q0, q1);
       }
       __threadfence();
       grid.sync();
-      __threadfence();
     }
     // Sweep finished: count the work-groups that rotated.  The counter of this
-    // sweep (zeroed by the host before the launch) is only incremented before
-    // the barrier and only read after it, so every work-group reads the same
-    // value and all of them leave the loop after the same number of barriers.
+    // sweep (zeroed before the launch) is only incremented before the barrier
+    // and only read after it, so every work-group reads the same value and all
+    // of them leave the loop after the same number of barriers.
     if (t == 0 && sh_rot) __hip_atomic_fetch_add(&s.rotflag[sweep], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __threadfence();
     grid.sync();
-    __threadfence();
     if (t == 0) sh_stop = __hip_atomic_load(&s.rotflag[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     __syncthreads();
     if (sh_stop) break;
+    dl = keep_level(s.cnorm, ncol, s.dmax, s.eps, s.defl * fro, kn, &shcnt, &shkap);
   }
   const int used = sweep + 1;
   // singular values: column norms
@@ -222,7 +414,6 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
   }
   __threadfence();
   grid.sync();
-  __threadfence();
   if (p != 0) return;
   // work-group 0: order, rank, normalisation, lambda, statistics
   __shared__ double shs[1024];
@@ -322,12 +513,59 @@ __global__ __launch_bounds__(256) void k_update_right(MpsView st, int n, const z
   }
 }
 
+// Forward mode (Jacobi on X = C~^H, no accumulation): column c of the rotated
+// X is s_c w_c^H, so w_c = conj(X[:, c]) / s_c.
+// k_update_left_t: B~_n[(a,i'), mu] = sum_k C[(a,i'), k] X[k, perm[mu]] / (s_{perm[mu]} nu).
+__global__ __launch_bounds__(256) void k_update_left_t(MpsView st, int n, const zd* C, int ldc, const zd* X,
+                                                       const double* sv, const int* perm, const int* gmeta,
+                                                       const double* gdmeta) {
+  const int a = st.dims[n], b = st.dims[n + 2];
+  const int r = gmeta[0];
+  const double nu = gdmeta[0];
+  const int Mr = 2 * a, Nc = r, K = 2 * b;
+  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  if (i0 >= Mr || j0 >= Nc) return;
+  auto fa = [&](int row, int k) { return C[(size_t)k * ldc + row]; };
+  auto fb = [&](int k, int mu) { return X[(size_t)perm[mu] * ldc + k]; };
+  zd acc[2][2];
+  ztile_acc(Mr, Nc, K, i0, j0, fa, fb, acc);
+  const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
+  zd* Bn = st.site(n);
+  const int dc = st.dcap;
+  for (int y = 0; y < 2; ++y) {
+    const int mu = c0 + y;
+    if (mu >= Nc) continue;
+    const double inv = 1.0 / (sv[perm[mu]] * nu);
+    for (int x = 0; x < 2; ++x) {
+      const int row = r0 + x;
+      if (row < Mr) Bn[(size_t)(row >> 1) * 2 * dc + (row & 1) * dc + mu] = zscale(acc[x][y], inv);
+    }
+  }
+}
+
+// k_update_right_t: B~_{n+1}[mu, j', beta] = conj(X[j'*b + beta, perm[mu]]) / s_{perm[mu]}.
+__global__ __launch_bounds__(256) void k_update_right_t(MpsView st, int n, const zd* X, int ldc, const double* sv,
+                                                        const int* perm, const int* gmeta) {
+  const int b = st.dims[n + 2];
+  const int r = gmeta[0];
+  const int mu = blockIdx.x;
+  if (mu >= r) return;
+  zd* Br = st.site(n + 1);
+  const int dc = st.dcap;
+  const int col = perm[mu];
+  const double inv = 1.0 / sv[col];
+  for (int e = threadIdx.x; e < 2 * b; e += 256) {
+    const int jp = e / b, be = e % b;
+    Br[(size_t)mu * 2 * dc + jp * dc + be] = zscale(zconj(X[(size_t)col * ldc + e]), inv);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Host launchers
 // ----------------------------------------------------------------------------
 int svd_width(int dcap) { return dcap <= 128 ? 8 : 4; }
 
-static SvdArgs svd_args(const MpsView& st, int bond, GateWork& w) {
+static SvdArgs svd_args(const MpsView& st, int bond, GateWork& w, GateMode mode) {
   SvdArgs s;
   s.A = w.A;
   s.lda = w.ldc;
@@ -349,35 +587,50 @@ static SvdArgs svd_args(const MpsView& st, int bond, GateWork& w) {
   s.nrm_part = w.nrm_part;
   const int tiles = (2 * st.dcap + ZT_M - 1) / ZT_M;
   s.nparts = tiles * tiles;
+  s.trans = mode == GATE_FWD ? 1 : 0;
+  s.defl = w.defl;
+  s.cnorm = w.cnorm;
   return s;
 }
 
 hipError_t launch_contract(const MpsView& st, const GateTable& gt, int g, const double* theta, GateWork& w,
-                           hipStream_t stream) {
+                           hipStream_t stream, GateMode mode) {
   const int tiles = (2 * st.dcap + ZT_M - 1) / ZT_M;
   hipLaunchKernelGGL(k_contract, dim3(tiles, tiles), dim3(256), 0, stream, st, gt, g, theta, w.C, w.A, w.ldc,
-                     w.nrm_part);
+                     w.nrm_part, mode == GATE_FWD ? 1 : 0, w.rotflag);
   return hipGetLastError();
 }
 
-hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stream) {
-  SvdArgs s = svd_args(st, bond, w);
-  const int W = svd_width(st.dcap);
-  const int P = (w.ncap + 2 * W - 1) / (2 * W);
-  const size_t shm = (size_t)2 * W * (w.ldc + w.ldv) * sizeof(zd);
-  void* args[] = {&s};
-  hipError_t e = hipMemsetAsync(w.rotflag, 0, 128 * sizeof(int), stream);
-  if (e != hipSuccess) return e;
-  if (W == 8)
-    e = hipLaunchCooperativeKernel((const void*)k_svd_jacobi<8>, dim3(P), dim3(256), args, shm, stream);
-  else
-    e = hipLaunchCooperativeKernel((const void*)k_svd_jacobi<4>, dim3(P), dim3(256), args, shm, stream);
-  return e;
+size_t svd_shared_bytes(int dcap, int ldc, int ldv, GateMode mode) {
+  const int W = svd_width(dcap);
+  return (size_t)2 * W * (ldc + (mode == GATE_TAPE ? ldv : 0)) * sizeof(zd);
 }
 
-hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t stream) {
+hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stream, GateMode mode) {
+  SvdArgs s = svd_args(st, bond, w, mode);
+  const int W = svd_width(st.dcap);
+  const int P = (w.ncap + 2 * W - 1) / (2 * W);
+  const size_t shm = svd_shared_bytes(st.dcap, w.ldc, w.ldv, mode);
+  void* args[] = {&s};
+  const void* f;
+  if (mode == GATE_TAPE)
+    f = W == 8 ? (const void*)k_svd_jacobi<8, true> : (const void*)k_svd_jacobi<4, true>;
+  else
+    f = W == 8 ? (const void*)k_svd_jacobi<8, false> : (const void*)k_svd_jacobi<4, false>;
+  return hipLaunchCooperativeKernel(f, dim3(P), dim3(256), args, shm, stream);
+}
+
+hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t stream, GateMode mode) {
   const int dc = st.dcap;
   const int tm = (2 * dc + ZT_M - 1) / ZT_M, tn = (dc + ZT_N - 1) / ZT_N;
+  if (mode == GATE_FWD) {
+    hipLaunchKernelGGL(k_update_left_t, dim3(tn, tm), dim3(256), 0, stream, st, bond, (const zd*)w.C, w.ldc,
+                       (const zd*)w.A, (const double*)w.sv, (const int*)w.perm, (const int*)w.gmeta,
+                       (const double*)w.gdmeta);
+    hipLaunchKernelGGL(k_update_right_t, dim3(dc), dim3(256), 0, stream, st, bond, (const zd*)w.A, w.ldc,
+                       (const double*)w.sv, (const int*)w.perm, (const int*)w.gmeta);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_update_left, dim3(tn, tm), dim3(256), 0, stream, st, bond, (const zd*)w.C, w.ldc,
                      (const zd*)w.V, w.ldv, (const int*)w.perm, (const int*)w.gmeta, (const double*)w.gdmeta);
   hipLaunchKernelGGL(k_update_right, dim3(dc), dim3(256), 0, stream, st, bond, (const zd*)w.V, w.ldv,
@@ -386,17 +639,20 @@ hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t s
 }
 
 hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, const double* theta,
-                       GateWork& w, hipStream_t stream) {
-  hipError_t e = launch_contract(st, gt, g, theta, w, stream);
+                       GateWork& w, hipStream_t stream, GateMode mode) {
+  hipError_t e = launch_contract(st, gt, g, theta, w, stream, mode);
   if (e != hipSuccess) return e;
-  e = launch_svd(st, bond, w, stream);
+  e = launch_svd(st, bond, w, stream, mode);
   if (e != hipSuccess) return e;
-  return launch_update(st, bond, w, stream);
+  return launch_update(st, bond, w, stream, mode);
 }
 
 hipError_t svd_set_attributes(int dcap, size_t shm) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_svd_jacobi<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)shm);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_svd_jacobi<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  const void* fs[4] = {(const void*)k_svd_jacobi<8, true>, (const void*)k_svd_jacobi<4, true>,
+                       (const void*)k_svd_jacobi<8, false>, (const void*)k_svd_jacobi<4, false>};
+  for (const void* f : fs) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }

@@ -69,7 +69,7 @@ struct mps_ctx {
   DevBuf b_prof;                           // [max samples][4] ints: rows, cols, sweeps
   GateWork gw{};
   SweepBuffers sb{};
-  DevBuf b_C, b_A, b_V, b_sv, b_perm, b_gmeta, b_gdmeta, b_rot, b_nrm, b_stats, b_stats2, b_theta;
+  DevBuf b_C, b_A, b_V, b_sv, b_perm, b_gmeta, b_gdmeta, b_rot, b_nrm, b_cnorm, b_stats, b_stats2, b_theta;
   DevBuf b_Lid, b_Rid, b_Lslots, b_Y, b_Yid, b_energy, b_termval;
   ~mps_ctx();
   void set_device();

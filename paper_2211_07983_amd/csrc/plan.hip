@@ -94,10 +94,10 @@ void plan_forward_energy(mps_plan* p, const double* theta, int n_theta, int on_d
     p->ckpt.ensure((size_t)std::max(1, p->n_seg) * p->ckpt_stride);
     for (int sg = 0; sg < p->n_seg; ++sg) {
       snapshot(p, sg, true);
-      run_gates(st, p->C, th, sg * K, std::min(G, (sg + 1) * K));
+      run_gates(st, p->C, th, sg * K, std::min(G, (sg + 1) * K), GATE_TAPE);
     }
   } else {
-    run_gates(st, p->C, th, 0, G);
+    run_gates(st, p->C, th, 0, G, GATE_TAPE);
   }
   HIPCHK(hipEventRecord(e1, s));
   run_energy(st, p->H);
