@@ -1,16 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: energy + gradient evaluations per second of the UCCSD-MPS
-workload (24 qubits, 12 orbitals, 12 electrons, D = 128) on one MI355X.
+"""Benchmark: energy + gradient evaluations per second of the UCCSD-MPS hot path
+on one MI355X.
 
-One step = one full evaluation of the hot path: product state, the 428183
-compiled two-qubit gates (contraction, one-sided Jacobi SVD, site update),
-29736 Pauli-term sweeps and the compensated energy sum, then the reverse pass
-(sweep adjoint, checkpoint recompute and gate adjoints, chain rule).
+Workloads (seeded synthetic problems, see vqe_inputs/configs.py):
+  c3 (default): 24 qubits (12 orbitals, 12 electrons), D = 128, 29736 Pauli
+      terms, 1818 parameters, 428183 compiled nearest-neighbour gates;
+  c2: 14 qubits (7 orbitals, 10 electrons), D = 64, 3381 terms, 140
+      parameters, 16899 gates.
+Truncation threshold eps = 1e-6 by default (the paper's setting, Sec. 5).
 
-Prints one JSON line.  The roofline object refers to the dominant kernel, the
-Jacobi SVD, timed live with HIP events around sampled launches on the stream
-the kernel runs on; the CPU baseline times the FP64 oracle on a bounded sample
-of the same workload on the host cores.
+One step = one full evaluation of the hot path: product state, every compiled
+gate (contraction, one-sided Jacobi SVD, site update) with a checkpoint every
+--ckpt-gates gates, the Pauli-term sweeps and the compensated energy sum, then
+the reverse pass (sweep adjoint, segment recompute with tape, gate adjoints,
+chain rule).  Inputs are resident on the device before the timed region.
+
+Prints one JSON line on stdout; progress lines (one per finished checkpoint
+segment, at most every 15 s) go to stderr.  The roofline object refers to the
+dominant kernel, the Jacobi SVD, timed with HIP events around sampled launches
+on the stream the kernel runs on; the CPU baseline times the FP64 oracle on a
+bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -23,28 +32,55 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector/matrix (256 CU x 2.4 GHz x 128 flop/clk)
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 (vector and matrix): 256 CU x 2.4 GHz x 128 flop/clk
+METRIC = "energy+grad evals/s (UCCSD-MPS 24q D=128) vs plain FP64; MFMA util %"
+WORKLOADS = {
+    "c3": "UCCSD-MPS 24 qubits (12 orbitals, 12 electrons), D=128",
+    "c2": "UCCSD-MPS 14 qubits (7 orbitals, 10 electrons), D=64",
+}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, gates, budget_s=25.0):
-    """Time the FP64 oracle (T3) on a bounded sample and scale to evals/s.
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    except Exception:
+        return int(os.environ.get("OMP_NUM_THREADS", "1"))
+
+
+def one_thread():
+    """BLAS limited to one thread: the oracle's small matrices run slower with
+    more (oversubscription), and one core is a defined setting to report."""
+    from threadpoolctl import threadpool_limits
+    return threadpool_limits(1)
+
+
+def cpu_baseline_full(prob, gates, eps):
+    """The FP64 oracle (T3) on the whole workload: one energy + gradient."""
+    from oracle import mps as T3
+    t0 = time.perf_counter()
+    T3.energy_grad(prob, gates, prob.theta, D=prob.bond_dim, eps=eps, ckpt=256)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "evals/s", "cores": blas_threads(), "kind": "oracle",
+            "sample": f"T3 FP64 oracle (NumPy/SciPy gesvd), one complete energy+gradient of the same workload "
+                      f"({gates.n_gates} gates, {prob.n_terms} terms, eps={eps:g}): {dt:.1f} s",
+            "seconds_per_eval": dt}
+
+
+def cpu_baseline_sample(prob, gates, eps, budget_s=25.0):
+    """The FP64 oracle (T3) on a bounded sample, scaled to one evaluation.
 
     Sample: a random right-canonical MPS with the saturated bond dimensions of the
-    24-qubit D=128 workload; a few gates on middle bonds (forward, recompute and
-    adjoint, all 256x256 SVDs) and a few hundred Pauli terms (energy and sweep
-    adjoint).  Per-evaluation time = G * (2 t_gate + t_adjoint) + K * (t_term + t_term_adj).
+    workload; gates on the middle bonds (forward with tape and gate adjoint, all
+    full-size SVDs) and a few hundred Pauli terms (energy and sweep adjoint).
+    Per evaluation: G * (2 t_gate + t_adjoint) + K * (t_term + t_term_adjoint).
     """
     import numpy as np
     from oracle import mps as T3
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
     rng = np.random.default_rng(12345)
     N, D = prob.n_qubits, prob.bond_dim
     dims = [1] + [min(2 ** (n + 1), 2 ** (N - n - 1), D) for n in range(N - 1)] + [1]
@@ -57,7 +93,6 @@ def cpu_baseline(prob, gates, budget_s=25.0):
         lam = np.sort(rng.random(b))[::-1] ** 4
         m.lam[n + 1] = lam / np.linalg.norm(lam)
     mid = N // 2
-    # gates on the middle bonds: forward (with tape) then adjoint
     t_gate, t_adj, n_g = 0.0, 0.0, 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < 0.45 * budget_s and n_g < 64:
@@ -67,11 +102,10 @@ def cpu_baseline(prob, gates, budget_s=25.0):
         tape = []
         saved = (m.B[n].copy(), m.B[n + 1].copy(), m.lam[n + 1].copy())
         t1 = time.perf_counter()
-        m.apply_gate(n, Q, D, prob.eps, tape)
+        m.apply_gate(n, Q, D, eps, tape)
         t2 = time.perf_counter()
-        t = tape[0]
-        T3.gate_backward(t, Q, dQ, rng.normal(size=m.B[n].shape) + 0j, rng.normal(size=m.B[n + 1].shape) + 0j,
-                         rng.normal(size=len(m.lam[n + 1])), check=0.0)
+        T3.gate_backward(tape[0], Q, dQ, rng.normal(size=m.B[n].shape) + 0j,
+                         rng.normal(size=m.B[n + 1].shape) + 0j, rng.normal(size=len(m.lam[n + 1])), check=0.0)
         t3 = time.perf_counter()
         m.B[n], m.B[n + 1], m.lam[n + 1] = saved
         t_gate += t2 - t1
@@ -79,7 +113,6 @@ def cpu_baseline(prob, gates, budget_s=25.0):
         n_g += 1
     t_gate /= n_g
     t_adj /= n_g
-    # Pauli terms: energy and naive sweep adjoint on a sample of terms
     K = prob.n_terms
     idx = rng.choice(K, size=min(K, 400), replace=False)
     L, R = m.identity_envs()
@@ -101,12 +134,12 @@ def cpu_baseline(prob, gates, budget_s=25.0):
     t_cot = (time.perf_counter() - t0) / n_c
     G = gates.n_gates
     per_eval = G * (2 * t_gate + t_adj) + K * (t_term + t_cot)
-    sample = (f"T3 FP64 oracle (NumPy/SciPy gesvd) on a random right-canonical MPS with the saturated bond "
-              f"dims of 24q D={D}: {n_g} middle-bond gate updates + adjoints (256x256 SVDs), {n_t} + {n_c} of "
-              f"{K} Pauli terms (energy, naive sweep adjoint); scaled to {G} gates x (forward + recompute + "
-              f"adjoint) + {K} terms per evaluation; t_gate={t_gate*1e3:.1f} ms, t_adj={t_adj*1e3:.1f} ms, "
-              f"t_term={t_term*1e3:.2f} ms, t_term_adj={t_cot*1e3:.2f} ms")
-    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": threads, "kind": "oracle", "sample": sample,
+    sample = (f"T3 FP64 oracle (NumPy/SciPy gesvd) on a random right-canonical MPS with the saturated bond dims of "
+              f"the workload: {n_g} middle-bond gate updates with tape + gate adjoints ({2 * dims[mid]}x"
+              f"{2 * dims[mid + 1]} SVDs), {n_t} + {n_c} of {K} Pauli terms (energy, naive sweep adjoint); scaled to "
+              f"{G} gates x (forward + recompute + adjoint) + {K} terms per evaluation; t_gate={t_gate*1e3:.1f} ms, "
+              f"t_adj={t_adj*1e3:.1f} ms, t_term={t_term*1e3:.2f} ms, t_term_adj={t_cot*1e3:.2f} ms")
+    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": blas_threads(), "kind": "oracle", "sample": sample,
             "seconds_per_eval": per_eval}
 
 
@@ -115,38 +148,51 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
+    ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--ckpt-gates", type=int, default=512)
     ap.add_argument("--profile-every", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the hot path runs on a single GPU in this build "
-              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+              "(the multi-GPU split is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     from vqe_inputs import configs
     from paper_2211_07983_amd import Context, Plan
     t = time.time()
-    prob, gates = configs.load("c3")
-    log(f"workload built in {time.time() - t:.1f}s: N={prob.n_qubits} K={prob.n_terms} "
-        f"n_theta={prob.n_theta} gates={gates.n_gates}")
+    prob, gates = configs.load(args.workload, eps=args.eps)
+    log(f"workload {args.workload} built in {time.time() - t:.1f}s: N={prob.n_qubits} K={prob.n_terms} "
+        f"n_theta={prob.n_theta} gates={gates.n_gates} D={prob.bond_dim} eps={prob.eps:g}")
     ctx = Context(0)
     ctx.set_profiling(args.profile_every)
+    last = [time.perf_counter(), None]
+
+    def progress(phase, done, total):
+        now = time.perf_counter()
+        if done == total or now - last[0] >= 15.0:
+            log(f"  {phase} segment {done}/{total} ({now - last[1]:.0f}s into the step)")
+            last[0] = now
+
+    ctx.set_progress(progress)
     plan = Plan(ctx, prob.occ, gates, prob.n_qubits, prob.ham_x, prob.ham_z, prob.ham_c, prob.c0,
                 prob.bond_dim, prob.eps, ckpt_gates=args.ckpt_gates)
     for w in range(args.warmup):
+        last[1] = time.perf_counter()
         e, g, st = plan.energy_grad(prob.theta)
-        log(f"warmup {w}: E={e:.12f} |g|={float((g ** 2).sum()) ** 0.5:.6e}")
+        log(f"warmup {w}: {time.perf_counter() - last[1]:.1f}s E={e:.12f}")
     stats = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ts = time.perf_counter()
+        last[1] = time.perf_counter()
         e, g, st = plan.energy_grad(prob.theta)
         stats.append(st)
-        log(f"step {k}: {time.perf_counter() - ts:.1f}s E={e:.12f} |g|={float((g ** 2).sum()) ** 0.5:.6e} "
+        log(f"step {k}: {time.perf_counter() - last[1]:.1f}s E={e:.12f} |g|={float((g ** 2).sum()) ** 0.5:.6e} "
             f"gates={st['t_gates_ms']/1e3:.1f}s sweep={st['t_sweep_ms']/1e3:.1f}s "
             f"backward={st['t_backward_ms']/1e3:.1f}s")
     T = time.perf_counter() - t0
+    ctx.set_progress(None)
     value = args.steps / T
     svd_ms = sum(s["prof_svd_ms"] for s in stats)
     svd_flop = sum(s["prof_svd_flop"] for s in stats)
@@ -160,11 +206,15 @@ def main():
                 "sampled_launches": n_svd}
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(prob, gates)
+        with one_thread():
+            if args.workload == "c2":
+                cpu = cpu_baseline_full(prob, gates, prob.eps)
+            else:
+                cpu = cpu_baseline_sample(prob, gates, prob.eps)
         log(f"cpu baseline: {cpu['value']:.3e} evals/s ({cpu['seconds_per_eval']:.0f} s/eval)")
-    last = stats[-1]
+    st = stats[-1]
     line = {
-        "metric": "energy+grad evals/s (UCCSD-MPS 24q D=128)",
+        "metric": METRIC,
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -176,13 +226,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded random integrals, JW Hamiltonian, spin-orbital UCCSD, theta~N(0,0.05))",
-        "config": {"workload": "UCCSD-MPS 24 qubits (12 orbitals, 12 electrons), D=128, eps=1e-12, "
-                               "K=29736 Pauli terms, 428183 NN gates, n_theta=1818, plain FP64",
+        "config": {"workload": WORKLOADS[args.workload] + f", eps={prob.eps:g}, K={prob.n_terms} Pauli terms, "
+                               f"{gates.n_gates} NN gates, n_theta={prob.n_theta}, plain FP64",
                    "energy": e, "grad_norm": float((g ** 2).sum()) ** 0.5,
-                   "t_gates_s": last["t_gates_ms"] / 1e3, "t_sweep_s": last["t_sweep_ms"] / 1e3,
-                   "t_backward_s": last["t_backward_ms"] / 1e3, "max_bond": last["max_bond"],
-                   "discarded_weight_sum": last["discarded_weight_sum"],
-                   "max_jacobi_sweeps": last["max_sweeps_used"], "ckpt_gates": args.ckpt_gates},
+                   "t_gates_s": st["t_gates_ms"] / 1e3, "t_sweep_s": st["t_sweep_ms"] / 1e3,
+                   "t_backward_s": st["t_backward_ms"] / 1e3, "max_bond": st["max_bond"],
+                   "discarded_weight_sum": st["discarded_weight_sum"],
+                   "max_jacobi_sweeps": st["max_sweeps_used"], "ckpt_gates": args.ckpt_gates},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

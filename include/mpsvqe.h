@@ -136,6 +136,13 @@ void mps_ctx_destroy(mps_ctx* ctx);
 /* Bracket every `every`-th SVD launch of a forward pass with HIP events and
  * report the sampled kernel time in mps_stats (0 = off, the default).       */
 mps_status mps_ctx_set_profiling(mps_ctx* ctx, int32_t every);
+/* Progress report of long calls: a plan's forward and reverse passes call
+ * fn(user, phase, done, total) on the calling thread after each checkpoint
+ * segment has finished on the device ("forward" / "backward", segments done
+ * out of total).  NULL fn = off (the default); with a callback set, the
+ * library waits for each segment to complete before reporting it.          */
+typedef void (*mps_progress_fn)(void* user, const char* phase, int64_t done, int64_t total);
+mps_status mps_ctx_set_progress(mps_ctx* ctx, mps_progress_fn fn, void* user);
 /* Text of the last error on ctx; valid until the next call on ctx.          */
 const char* mps_last_error(const mps_ctx* ctx);
 

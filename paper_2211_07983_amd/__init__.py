@@ -108,6 +108,16 @@ class Context:
     def set_profiling(self, every):
         self.check(self._lib.mps_ctx_set_profiling(self.h, int(every)))
 
+    def set_progress(self, fn):
+        """fn(phase: str, done: int, total: int) after each checkpoint segment of a
+        plan's forward and reverse passes (None = off)."""
+        if fn is None:
+            self._progress = None
+            self.check(self._lib.mps_ctx_set_progress(self.h, _abi.ProgressFn(), None))
+            return
+        self._progress = _abi.ProgressFn(lambda user, phase, done, total: fn(phase.decode(), done, total))
+        self.check(self._lib.mps_ctx_set_progress(self.h, self._progress, None))
+
     def check(self, status):
         if status != 0:
             raise MPSError(status, self._lib.mps_last_error(self.h).decode())

@@ -12,11 +12,15 @@ STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_EDEVIC
                 -4: "MPS_ENOCONV", -5: "MPS_EDEGEN"}
 
 EXPORTS = [
-    "mps_ctx_create", "mps_ctx_destroy", "mps_ctx_set_profiling", "mps_last_error", "mps_init_product",
+    "mps_ctx_create", "mps_ctx_destroy", "mps_ctx_set_profiling", "mps_ctx_set_progress", "mps_last_error", "mps_init_product",
     "mps_apply_circuit", "mps_expect_paulisum", "mps_plan_create", "mps_energy_grad",
     "mps_plan_energy", "mps_state_export", "mps_state_size", "mps_state_qubits",
     "mps_state_free", "mps_plan_free",
 ]
+
+
+# void (*)(void* user, const char* phase, int64_t done, int64_t total)
+ProgressFn = C.CFUNCTYPE(None, C.c_void_p, C.c_char_p, C.c_int64, C.c_int64)
 
 
 class Trunc(C.Structure):
@@ -80,6 +84,8 @@ def load(path=LIB_PATH):
     lib.mps_ctx_destroy.restype = None
     lib.mps_ctx_set_profiling.argtypes = [vp, C.c_int32]
     lib.mps_ctx_set_profiling.restype = C.c_int32
+    lib.mps_ctx_set_progress.argtypes = [vp, ProgressFn, vp]
+    lib.mps_ctx_set_progress.restype = C.c_int32
     lib.mps_last_error.argtypes = [vp]
     lib.mps_last_error.restype = C.c_char_p
     lib.mps_init_product.argtypes = [vp, C.c_int32, C.POINTER(C.c_uint8), C.POINTER(Trunc), C.POINTER(vp)]

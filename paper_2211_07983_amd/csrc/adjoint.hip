@@ -1020,6 +1020,10 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
       hipLaunchKernelGGL(k_adj_finish, dim3(1), dim3(256), 0, s, W, lb_out, dc, nparts, gphi, g, p->C.kind_h[g]);
     }
     HIPCHK(hipGetLastError());
+    if (ctx->progress) {
+      HIPCHK(hipStreamSynchronize(s));
+      ctx->progress(ctx->progress_user, "backward", p->n_seg - sg, p->n_seg);
+    }
   }
   if (!A.chain_built) build_chain(p, A);
   double* gd_dev = (double*)p->grad.ensure((size_t)std::max(1, p->n_theta) * sizeof(double));

@@ -42,11 +42,9 @@ struct GateWork {
   double* gdmeta; // [4]
   int* rotflag;   // [128]
   double* nrm_part; // [256] per-tile |A|^2 partial sums of k_contract
-  double* cnorm;    // [ncap] column norms of the Jacobi sweeps
   GateStats* stats;
   int ldc, ldv, ncap;
   double eps, tol;
-  double defl;      // convergence vote ignores columns with |a|^2 <= defl |A|_F^2
   int dmax, max_sweeps;
 };
 
@@ -71,8 +69,6 @@ struct SvdArgs {
   const double* nrm_part;
   int nparts;
   int trans;         // 1: the matrix is C~^H (columns = rows of C~)
-  double defl;       // columns with |a|^2 <= defl |A|_F^2 do not count for convergence
-  double* cnorm;     // [ncap] squared column norms at the end of each sweep
 };
 
 // ----------------------------------------------------------------------------

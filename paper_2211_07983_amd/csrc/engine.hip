@@ -63,21 +63,13 @@ void mps_ctx::ensure_gate_work(int dcap, const mps_trunc& tr, int max_sweeps) {
   gw.gdmeta = (double*)b_gdmeta.ensure(16 * sizeof(double));
   gw.rotflag = (int*)b_rot.ensure(128 * sizeof(int));
   gw.nrm_part = (double*)b_nrm.ensure(256 * sizeof(double));
-  gw.cnorm = (double*)b_cnorm.ensure((size_t)ncap * sizeof(double));
   gw.stats = (GateStats*)b_stats.ensure(sizeof(GateStats));
   gw.eps = tr.eps;
   gw.dmax = tr.d_max;
   gw.max_sweeps = std::min(std::max(max_sweeps, 1), 100);   // per-sweep counters: 128 slots
   gw.tol = std::max(1e-15, 8.0 * std::sqrt((double)ldc) * 2.220446049250313e-16);
-  // Columns below 1e-2 eps in norm are discarded whatever their final value;
-  // once only rotations that cannot move the other columns remain, the kept
-  // part has converged.
-  gw.defl = (1e-2 * tr.eps) * (1e-2 * tr.eps);
-  const size_t shm = svd_shared_bytes(dcap, ldc, ncap, GATE_TAPE);
-  if (shm > shm_set) {
-    HIPCHK(svd_set_attributes(dcap, shm));
-    shm_set = shm;
-  }
+  // the kernel width depends on dcap: set the LDS limit of this width's kernels
+  HIPCHK(svd_set_attributes(dcap, svd_shared_bytes(dcap, ldc, ncap, GATE_TAPE)));
 }
 
 void mps_ctx::reset_stats() { HIPCHK(hipMemsetAsync(gw.stats, 0, sizeof(GateStats), stream)); }
@@ -397,6 +389,13 @@ void mps_ctx_destroy(mps_ctx* ctx) {
 }
 
 const char* mps_last_error(const mps_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mps_status mps_ctx_set_progress(mps_ctx* ctx, mps_progress_fn fn, void* user) {
+  if (!ctx) return MPS_EINVAL;
+  ctx->progress = fn;
+  ctx->progress_user = user;
+  return MPS_OK;
+}
 
 mps_status mps_ctx_set_profiling(mps_ctx* ctx, int32_t every) {
   if (!ctx || every < 0) return MPS_EINVAL;

@@ -106,11 +106,13 @@ __device__ inline double swz16_add(double v) {   // lane l <-> l ^ 16
 }
 template <int TPP>
 __device__ inline void group_sum4(double& a, double& b, double& c, double& d) {
-  static_assert(TPP == 16 || TPP == 32 || TPP == 64, "group size");
+  static_assert(TPP == 8 || TPP == 16 || TPP == 32 || TPP == 64, "group size");
   a = dpp_add<0xB1>(a); b = dpp_add<0xB1>(b); c = dpp_add<0xB1>(c); d = dpp_add<0xB1>(d);      // quad [1,0,3,2]
   a = dpp_add<0x4E>(a); b = dpp_add<0x4E>(b); c = dpp_add<0x4E>(c); d = dpp_add<0x4E>(d);      // quad [2,3,0,1]
   a = dpp_add<0x141>(a); b = dpp_add<0x141>(b); c = dpp_add<0x141>(c); d = dpp_add<0x141>(d);  // half-row mirror
-  a = dpp_add<0x140>(a); b = dpp_add<0x140>(b); c = dpp_add<0x140>(c); d = dpp_add<0x140>(d);  // row mirror
+  if (TPP >= 16) {
+    a = dpp_add<0x140>(a); b = dpp_add<0x140>(b); c = dpp_add<0x140>(c); d = dpp_add<0x140>(d);  // row mirror
+  }
   if (TPP >= 32) {
     a = swz16_add(a); b = swz16_add(b); c = swz16_add(c); d = swz16_add(d);
   }
@@ -126,11 +128,8 @@ __device__ inline void group_sum4(double& a, double& b, double& c, double& d) {
 //   x' = c x - c h conj(gamma) y,    y' = c h gamma x + c y
 // makes x'^H y' = 0.  Returns false when the pair is already orthogonal
 // (|gamma| <= tol sqrt(alpha beta)) or negligible (|gamma| <= floor_g).
-// `sig` tells whether the rotation can still change a column that matters:
-// one of the two columns is above the deflation level and either both are or
-// the relative change of the larger one exceeds tol.
 __device__ inline bool jacobi_rotation(double al, double be, double gr, double gi, double tol, double floor_g,
-                                       double dl, double& c, zd& p, zd& q, bool& sig) {
+                                       double& c, zd& p, zd& q) {
   const double g2 = fma(gr, gr, gi * gi);
   const double ab = al * be;
   if (!(ab > 1e-300) || g2 <= tol * tol * ab || g2 <= floor_g * floor_g) return false;
@@ -141,8 +140,6 @@ __device__ inline bool jacobi_rotation(double al, double be, double gr, double g
   const double ch = c * h;
   p = zmk(ch * gr, -ch * gi);    // c h conj(gamma)
   q = zmk(ch * gr, ch * gi);     // c h gamma
-  const double mn = fmin(al, be), mx = fmax(al, be);
-  sig = mx > dl && (mn > dl || g2 * mn > tol * tol * mx * mx * mx);
   return true;
 }
 
@@ -193,41 +190,6 @@ __device__ inline void store_blocks(zd* dst, int ldd, const zd* src, int lsrc, i
   }
 }
 
-// Deflation level for the next sweep's convergence vote.  From the squared
-// column norms cn at the end of a sweep: r = min(dmax, #{cn > eps^2}) >= 1
-// columns would be kept and kappa is the r-th largest norm.  Pairs whose two
-// columns both lie below 1e-2 kappa (ten times below the cut in singular
-// value) can neither enter the kept set nor move it, so once only such
-// rotations remain the kept part has converged.  Every work-group evaluates
-// this on the same data and reaches the same value.
-__device__ inline double keep_level(const double* cn, int ncol, int dmax, double eps, double base, double* kn,
-                                    int* shcnt, double* shkap) {
-  const int t = threadIdx.x;
-  if (t == 0) {
-    *shcnt = 0;
-    *shkap = 0.0;
-  }
-  for (int c = t; c < ncol; c += 256) kn[c] = cn[c];
-  __syncthreads();
-  int cnt = 0;
-  for (int c = t; c < ncol; c += 256) cnt += kn[c] > eps * eps;
-  if (cnt) atomicAdd(shcnt, cnt);
-  __syncthreads();
-  int r = *shcnt < dmax ? *shcnt : dmax;
-  if (r < 1) r = 1;
-  for (int c = t; c < ncol; c += 256) {
-    const double v = kn[c];
-    int rank = 0;
-    for (int q = 0; q < ncol; ++q) {
-      const double u = kn[q];
-      rank += (u > v) || (u == v && q < c);
-    }
-    if (rank == r - 1) *shkap = v;
-  }
-  __syncthreads();
-  return fmax(1e-2 * *shkap, base);
-}
-
 template <int W, bool ACC>
 __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
   constexpr int TPP = 256 / W;     // threads per column pair
@@ -254,10 +216,6 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
   double fro = 0.0;
   for (int q = 0; q < s.nparts; ++q) fro += s.nrm_part[q];
   const double floor_g = 1e-28 * fro;
-  double dl = s.defl * fro;
-  __shared__ double kn[512];
-  __shared__ int shcnt;
-  __shared__ double shkap;
   int sweep = 0;
   for (; sweep < s.max_sweeps; ++sweep) {
     if (t == 0) sh_rot = 0;
@@ -294,8 +252,7 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
             group_sum4<TPP>(al, be, gr, gi);
             double c;
             zd pp, qq;
-            bool sig;
-            if (jacobi_rotation(al, be, gr, gi, tol, floor_g, dl, c, pp, qq, sig)) {
+            if (jacobi_rotation(al, be, gr, gi, tol, floor_g, c, pp, qq)) {
               for (int rr = lt; rr < M; rr += TPP) {
                 const zd u = x[rr], v = y[rr];
                 x[rr] = rot_x(u, v, c, pp);
@@ -310,7 +267,7 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
                   yv[rr] = rot_y(u, v, c, qq);
                 }
               }
-              rot |= sig;
+              rot = true;
             }
             __syncthreads();
           }
@@ -341,8 +298,7 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
             group_sum4<TPP>(al, be, gr, gi);
             double c;
             zd pp, qq;
-            bool sig;
-            if (jacobi_rotation(al, be, gr, gi, tol, floor_g, dl, c, pp, qq, sig)) {
+            if (jacobi_rotation(al, be, gr, gi, tol, floor_g, c, pp, qq)) {
 #pragma unroll
               for (int i = 0; i < RPT; ++i) {
                 const int r = lt + i * TPP;
@@ -362,7 +318,7 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
                   }
                 }
               }
-              rot |= sig;
+              rot = true;
             }
             __syncthreads();
           }
@@ -375,16 +331,6 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
           __syncthreads();
         }
         if (rot && lt == 0) sh_rot = 1;
-        if (k == 2 * P - 2) {
-          // squared norms of the 2W columns after the sweep's last round
-          for (int c = pr; c < 2 * W; c += W) {
-            double acc = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-            for (int r = lt; r < M; r += TPP) acc += zabs2(Al[c * mpad + r]);
-            group_sum4<TPP>(acc, d1, d2, d3);
-            const int gc = (c < W ? q0 : q1) * W + (c % W);
-            if (lt == 0 && gc < ncol) s.cnorm[gc] = acc;
-          }
-        }
         store_blocks(s.A, s.lda, Al, mpad, M, ncol, W, q0, q1);
         if (ACC) store_blocks(s.V, s.ldv, Vl, vpad, ncol, ncol, W, q0, q1);
       }
@@ -401,7 +347,6 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
     if (t == 0) sh_stop = __hip_atomic_load(&s.rotflag[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     __syncthreads();
     if (sh_stop) break;
-    dl = keep_level(s.cnorm, ncol, s.dmax, s.eps, s.defl * fro, kn, &shcnt, &shkap);
   }
   const int used = sweep + 1;
   // singular values: column norms
@@ -563,7 +508,20 @@ __global__ __launch_bounds__(256) void k_update_right_t(MpsView st, int n, const
 // ----------------------------------------------------------------------------
 // Host launchers
 // ----------------------------------------------------------------------------
-int svd_width(int dcap) { return dcap <= 128 ? 8 : 4; }
+// Column-block width: two blocks of W columns (and of V when accumulating)
+// fill at most 128 KiB of LDS, and each pair group of 256 / W threads holds
+// eight rows per thread, so 2 dcap <= 8 * 256 / W.
+int svd_width(int dcap) { return dcap <= 32 ? 32 : dcap <= 64 ? 16 : dcap <= 128 ? 8 : 4; }
+
+static const void* svd_kernel(int W, GateMode mode) {
+  const bool acc = mode == GATE_TAPE;
+  switch (W) {
+    case 32: return acc ? (const void*)k_svd_jacobi<32, true> : (const void*)k_svd_jacobi<32, false>;
+    case 16: return acc ? (const void*)k_svd_jacobi<16, true> : (const void*)k_svd_jacobi<16, false>;
+    case 8: return acc ? (const void*)k_svd_jacobi<8, true> : (const void*)k_svd_jacobi<8, false>;
+    default: return acc ? (const void*)k_svd_jacobi<4, true> : (const void*)k_svd_jacobi<4, false>;
+  }
+}
 
 static SvdArgs svd_args(const MpsView& st, int bond, GateWork& w, GateMode mode) {
   SvdArgs s;
@@ -588,8 +546,6 @@ static SvdArgs svd_args(const MpsView& st, int bond, GateWork& w, GateMode mode)
   const int tiles = (2 * st.dcap + ZT_M - 1) / ZT_M;
   s.nparts = tiles * tiles;
   s.trans = mode == GATE_FWD ? 1 : 0;
-  s.defl = w.defl;
-  s.cnorm = w.cnorm;
   return s;
 }
 
@@ -612,12 +568,7 @@ hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stre
   const int P = (w.ncap + 2 * W - 1) / (2 * W);
   const size_t shm = svd_shared_bytes(st.dcap, w.ldc, w.ldv, mode);
   void* args[] = {&s};
-  const void* f;
-  if (mode == GATE_TAPE)
-    f = W == 8 ? (const void*)k_svd_jacobi<8, true> : (const void*)k_svd_jacobi<4, true>;
-  else
-    f = W == 8 ? (const void*)k_svd_jacobi<8, false> : (const void*)k_svd_jacobi<4, false>;
-  return hipLaunchCooperativeKernel(f, dim3(P), dim3(256), args, shm, stream);
+  return hipLaunchCooperativeKernel(svd_kernel(W, mode), dim3(P), dim3(256), args, shm, stream);
 }
 
 hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t stream, GateMode mode) {
@@ -648,10 +599,9 @@ hipError_t launch_gate(const MpsView& st, const GateTable& gt, int g, int bond, 
 }
 
 hipError_t svd_set_attributes(int dcap, size_t shm) {
-  const void* fs[4] = {(const void*)k_svd_jacobi<8, true>, (const void*)k_svd_jacobi<4, true>,
-                       (const void*)k_svd_jacobi<8, false>, (const void*)k_svd_jacobi<4, false>};
-  for (const void* f : fs) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  const int W = svd_width(dcap);
+  for (GateMode m : {GATE_TAPE, GATE_FWD}) {
+    hipError_t e = hipFuncSetAttribute(svd_kernel(W, m), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -60,16 +60,17 @@ struct mps_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  size_t shm_set = 0;
   size_t sweep_budget = (size_t)6 << 30;   // bytes for per-term environments
   int last_degen_grad = 0;
   int prof_every = 0;                      // sample every k-th SVD launch (0 = off)
+  mps_progress_fn progress = nullptr;      // per-segment progress report (nullable)
+  void* progress_user = nullptr;
   std::vector<hipEvent_t> prof_ev;         // [2 * samples]
   std::vector<int> prof_n;                 // samples taken in the current call
   DevBuf b_prof;                           // [max samples][4] ints: rows, cols, sweeps
   GateWork gw{};
   SweepBuffers sb{};
-  DevBuf b_C, b_A, b_V, b_sv, b_perm, b_gmeta, b_gdmeta, b_rot, b_nrm, b_cnorm, b_stats, b_stats2, b_theta;
+  DevBuf b_C, b_A, b_V, b_sv, b_perm, b_gmeta, b_gdmeta, b_rot, b_nrm, b_stats, b_stats2, b_theta;
   DevBuf b_Lid, b_Rid, b_Lslots, b_Y, b_Yid, b_energy, b_termval;
   ~mps_ctx();
   void set_device();

@@ -95,6 +95,10 @@ void plan_forward_energy(mps_plan* p, const double* theta, int n_theta, int on_d
     for (int sg = 0; sg < p->n_seg; ++sg) {
       snapshot(p, sg, true);
       run_gates(st, p->C, th, sg * K, std::min(G, (sg + 1) * K), GATE_TAPE);
+      if (ctx->progress) {
+        HIPCHK(hipStreamSynchronize(s));
+        ctx->progress(ctx->progress_user, "forward", sg + 1, p->n_seg);
+      }
     }
   } else {
     run_gates(st, p->C, th, 0, G, GATE_TAPE);

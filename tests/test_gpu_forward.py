@@ -48,6 +48,18 @@ def test_forward_energy_matches_oracle(ctx, name):
         assert np.abs(lam[k] - ref).max() <= 1e-10
 
 
+def test_forward_paper_threshold_matches_oracle(ctx):
+    """Energy-only forward (Jacobi on C~^H without V) at eps = 1e-6, where the
+    threshold truncates thousands of gates: E and final bonds against the oracle."""
+    p, g = configs.load("c2", eps=configs.PAPER_EPS)
+    gold = golden()["c2_paper"]
+    e, _, s1, s2, st = gpu_energy(ctx, p, g, p.theta)
+    assert s1["gates_truncated"] > 1000
+    assert rel(e, gold["E"]) <= 1e-10
+    dims, _, _ = st.export()
+    assert list(dims[1:-1]) == gold["bonds"]
+
+
 def test_forward_term_values_match_oracle_c1(ctx):
     from oracle import mps
     p, g = configs.load("c1")

@@ -39,6 +39,20 @@ def test_energy_grad_matches_oracle(ctx, name):
     plan.free()
 
 
+def test_paper_threshold_energy_grad_matches_oracle(ctx):
+    """C2 at eps = 1e-6 (the paper's setting): truncation by the threshold on
+    every bond; E_D and g_D against the oracle at the same threshold."""
+    p, g = configs.load("c2", eps=configs.PAPER_EPS)
+    gold = golden()["c2_paper"]
+    assert gold["eps"] == p.eps
+    plan = make_plan(ctx, p, g, ckpt_gates=512)
+    e, grad, st = plan.energy_grad(p.theta)
+    assert st["gates_truncated"] > 1000
+    assert rel(e, gold["E"]) <= 1e-10
+    assert grad_ok(grad, np.array(gold["grad"]))
+    plan.free()
+
+
 def test_checkpoint_interval_invariance(ctx):
     p, g = configs.load("c1")
     a = make_plan(ctx, p, g, ckpt_gates=7).energy_grad(p.theta)[1]
