@@ -227,28 +227,6 @@ struct GateDims {
   double nu;
 };
 
-__global__ void k_tape_inputs(MpsView st, int n, zd* Bl, zd* Br, double* lam, int* meta) {
-  const int a = st.dims[n], m = st.dims[n + 1], b = st.dims[n + 2];
-  const int dc = st.dcap;
-  const size_t site = (size_t)dc * 2 * dc;
-  const zd* s0 = st.site(n);
-  const zd* s1 = st.site(n + 1);
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < site; e += (size_t)gridDim.x * blockDim.x) {
-    const int row = (int)(e / dc), col = (int)(e % dc);
-    const int l = row >> 1;
-    if (l < a && col < m) Bl[e] = s0[e];
-    if (l < m && col < b) Br[e] = s1[e];
-  }
-  if (blockIdx.x == 0) {
-    for (int q = threadIdx.x; q < a; q += blockDim.x) lam[q] = st.lam[(size_t)n * dc + q];
-    if (threadIdx.x == 0) {
-      meta[4] = a;
-      meta[5] = m;
-      meta[6] = b;
-    }
-  }
-}
-
 // A1: Wbar[mu, c] = sum_row conj(Bbar_n[row, mu]) / nu * C[row, c] + Bbar_{n+1}[mu, c]
 __global__ __launch_bounds__(256) void k_adj_wbar(GateRec R, AdjWork W, const zd* Bbn, const zd* Bbn1, GateDims d,
                                                   int dc, int ldc) {
@@ -849,29 +827,7 @@ static void run_sweep_adjoint(mps_plan* p, const std::vector<int>& dims) {
 // ============================================================================
 // Host: gate adjoint over checkpoint segments
 // ============================================================================
-struct TapeLayout {
-  size_t oBl, oBr, olam, oC, oA, oV, osv, operm, ometa, odmeta, rec;
-};
-
 static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
-
-static TapeLayout tape_layout(int dc, int ncap, int ldc, int ldv) {
-  TapeLayout L;
-  size_t o = 0;
-  const size_t site = (size_t)dc * 2 * dc * sizeof(zd);
-  L.oBl = o; o = al256(o + site);
-  L.oBr = o; o = al256(o + site);
-  L.olam = o; o = al256(o + dc * sizeof(double));
-  L.oC = o; o = al256(o + (size_t)ncap * ldc * sizeof(zd));
-  L.oA = o; o = al256(o + (size_t)ncap * ldc * sizeof(zd));
-  L.oV = o; o = al256(o + (size_t)ncap * ldv * sizeof(zd));
-  L.osv = o; o = al256(o + ncap * sizeof(double));
-  L.operm = o; o = al256(o + ncap * sizeof(int));
-  L.ometa = o; o = al256(o + 16 * sizeof(int));
-  L.odmeta = o; o = al256(o + 16 * sizeof(double));
-  L.rec = o;
-  return L;
-}
 
 static GateRec rec_at(char* base, const TapeLayout& L, int k) {
   char* r = base + (size_t)k * L.rec;
@@ -927,7 +883,32 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   GateWork gw = ctx->gw;
   const TapeLayout L = tape_layout(dc, gw.ncap, gw.ldc, gw.ldv);
   const int K = p->opts.ckpt_gates;
-  char* tape = (char*)p->tape.ensure((size_t)K * L.rec);
+  // Segments are recomputed nl at a time (lanes), all lanes advancing one gate
+  // per launch; the adjoint then walks the batch's segments in reverse order.
+  const size_t seg_bytes = (size_t)K * L.rec;
+  const size_t tape_budget = (size_t)64 << 30;
+  int nlanes = std::min({p->n_seg, lanes_max(dc), 64, (int)std::max<size_t>(1, tape_budget / seg_bytes)});
+  nlanes = std::max(1, nlanes);
+  char* tape = (char*)p->tape.ensure((size_t)nlanes * seg_bytes);
+  while ((int)p->replays.size() < nlanes) p->replays.push_back(plan_new_state(ctx, N, st->trunc, nullptr));
+  const size_t aux_lane = 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats) + 64;
+  char* aux = (char*)p->lane_aux.ensure((size_t)nlanes * aux_lane + 64);
+  int* lane_err = (int*)(aux + (size_t)nlanes * aux_lane);
+  HIPCHK(hipMemsetAsync(lane_err, 0, sizeof(int), s));
+  GateLane* lanes_d = (GateLane*)p->lanes_dev.ensure((size_t)nlanes * sizeof(GateLane));
+  p->lanes_h.resize(nlanes);
+  LaneConst lc;
+  lc.gt = p->C.tab;
+  lc.theta = (const double*)p->theta.p;
+  lc.L = L;
+  lc.ldc = gw.ldc;
+  lc.ldv = gw.ldv;
+  lc.ncap = gw.ncap;
+  lc.dmax = gw.dmax;
+  lc.max_sweeps = gw.max_sweeps;
+  lc.nparts = ((2 * dc + ZT_M - 1) / ZT_M) * ((2 * dc + ZT_M - 1) / ZT_M);
+  lc.eps = gw.eps;
+  lc.tol = gw.tol;
   const int ldw = gw.ncap;
   AdjWork W;
   {
@@ -952,77 +933,84 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   }
   double* gphi = (double*)p->gphi.ensure((size_t)std::max(1, p->C.G) * sizeof(double));
   HIPCHK(hipMemsetAsync(gphi, 0, p->gphi.bytes, s));
-  GateStats* scratch = (GateStats*)ctx->b_stats2.ensure(sizeof(GateStats));
   zd* Bbar = (zd*)p->Bbar.p;
   double* lambar = (double*)p->lambar.p;
-  mps_state* rp = p->replay;
-  MpsView rv = view_of(rp);
   const double* th = (const double*)p->theta.p;
-  std::vector<int> meta(16);
-  std::vector<double> dmeta(16);
-  for (int sg = p->n_seg - 1; sg >= 0; --sg) {
-    const int g0 = sg * K, g1 = std::min(p->C.G, (sg + 1) * K);
-    plan_restore(p, sg, rp);
-    HIPCHK(hipMemsetAsync(scratch, 0, sizeof(GateStats), s));
-    for (int g = g0; g < g1; ++g) {
-      GateRec R = rec_at(tape, L, g - g0);
-      const int n = p->C.bond_h[g];
-      hipLaunchKernelGGL(k_tape_inputs, dim3(64), dim3(256), 0, s, rv, n, R.Bl, R.Br, R.lam, R.meta);
-      GateWork tw = gw;
-      tw.C = R.C;
-      tw.A = R.A;
-      tw.V = R.V;
-      tw.sv = R.sv;
-      tw.perm = R.perm;
-      tw.gmeta = R.meta;
-      tw.gdmeta = R.dmeta;
-      tw.stats = scratch;
-      HIPCHK(launch_gate(rv, p->C.tab, g, n, th, tw, s));
+  std::vector<int> meta((size_t)nlanes * K * 16);
+  std::vector<double> dmeta((size_t)nlanes * K * 16);
+  for (int hi = p->n_seg - 1; hi >= 0; hi -= nlanes) {
+    const int lo = std::max(0, hi - nlanes + 1), nl = hi - lo + 1;
+    int steps = 0;
+    for (int l = 0; l < nl; ++l) {
+      const int sg = lo + l;
+      mps_state* rp = p->replays[l];
+      plan_restore(p, sg, rp);
+      GateLane& ln = p->lanes_h[l];
+      ln.st = view_of(rp);
+      ln.g0 = sg * K;
+      ln.ng = std::min(p->C.G, (sg + 1) * K) - sg * K;
+      ln.tape = tape + (size_t)l * seg_bytes;
+      char* la = aux + (size_t)l * aux_lane;
+      ln.rotflag = (int*)la;
+      ln.nrm_part = (double*)(la + 128 * sizeof(int));
+      ln.stats = (GateStats*)(la + 128 * sizeof(int) + 256 * sizeof(double));
+      ln.bar = (unsigned*)(la + 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats));
+      ln.err = lane_err;
+      steps = std::max(steps, ln.ng);
     }
-    // sizes of the segment's gates
-    std::vector<GateDims> gd(g1 - g0);
-    for (int g = g0; g < g1; ++g) {
-      GateRec R = rec_at(tape, L, g - g0);
-      HIPCHK(hipMemcpyAsync(meta.data(), R.meta, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(dmeta.data(), R.dmeta, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      GateDims d;
-      d.n = p->C.bond_h[g];
-      d.r = meta[0];
-      d.a = meta[4];
-      d.m = meta[5];
-      d.b = meta[6];
-      d.nu = dmeta[0];
-      gd[g - g0] = d;
+    HIPCHK(hipMemcpyAsync(lanes_d, p->lanes_h.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
+    for (int step = 0; step < steps; ++step) HIPCHK(launch_gate_lanes(lanes_d, nl, lc, step, s));
+    // sizes of the batch's gates (one strided copy per lane and field)
+    for (int l = 0; l < nl; ++l) {
+      const GateLane& ln = p->lanes_h[l];
+      HIPCHK(hipMemcpy2DAsync(meta.data() + (size_t)l * K * 16, 16 * sizeof(int), ln.tape + L.ometa, L.rec,
+                              16 * sizeof(int), ln.ng, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpy2DAsync(dmeta.data() + (size_t)l * K * 16, 16 * sizeof(double), ln.tape + L.odmeta, L.rec,
+                              16 * sizeof(double), ln.ng, hipMemcpyDeviceToHost, s));
     }
-    for (int g = g1 - 1; g >= g0; --g) {
-      GateRec R = rec_at(tape, L, g - g0);
-      const GateDims d = gd[g - g0];
-      const int n = d.n;
-      zd* Bbn = Bbar + (size_t)n * site;
-      zd* Bbn1 = Bbar + (size_t)(n + 1) * site;
-      double* lb_out = lambar + (size_t)(n + 1) * dc;
-      double* lb_in = lambar + (size_t)n * dc;
-      const int M = 2 * d.a, nb = 2 * d.b;
-      hipLaunchKernelGGL(k_adj_wbar, gemm_grid(d.r, nb), dim3(256), 0, s, R, W, (const zd*)Bbn, (const zd*)Bbn1, d, dc, gw.ldc);
-      hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, s, R, W, (const zd*)Bbn1, (const double*)lb_out, d, dc, gw.ldv);
-      hipLaunchKernelGGL(k_adj_K, gemm_grid(nb, d.r), dim3(256), 0, s, R, W, d, dc, gw.ldv);
-      hipLaunchKernelGGL(k_adj_kscale, dim3(1), dim3(256), 0, s, W, d, dc);
-      hipLaunchKernelGGL(k_adj_phi, dim3((nb * nb + 255) / 256), dim3(256), 0, s, R, W, d, dc, p->opts.broaden, gw.stats);
-      hipLaunchKernelGGL(k_adj_T, gemm_grid(M, nb), dim3(256), 0, s, R, W, d, gw.ldc);
-      hipLaunchKernelGGL(k_adj_Mbar, gemm_grid(M, nb), dim3(256), 0, s, R, W, d, gw.ldv);
-      hipLaunchKernelGGL(k_adj_Cbar, gemm_grid(M, nb), dim3(256), 0, s, R, W, (const zd*)Bbn, d, dc, gw.ldv);
-      hipLaunchKernelGGL(k_adj_lambar, dim3(d.a), dim3(256), 0, s, R, W, d, lb_in, gw.ldc);
-      const int nparts = (d.a * d.b + 255) / 256;
-      hipLaunchKernelGGL(k_adj_theta, dim3(nparts), dim3(256), 0, s, R, W, p->C.tab, g, th, d, gw.ldc);
-      hipLaunchKernelGGL(k_adj_Bl, gemm_grid(M, d.m), dim3(256), 0, s, R, W, Bbn, d, dc);
-      hipLaunchKernelGGL(k_adj_Br, gemm_grid(d.m, nb), dim3(256), 0, s, R, W, Bbn1, d, dc);
-      hipLaunchKernelGGL(k_adj_finish, dim3(1), dim3(256), 0, s, W, lb_out, dc, nparts, gphi, g, p->C.kind_h[g]);
-    }
-    HIPCHK(hipGetLastError());
-    if (ctx->progress) {
-      HIPCHK(hipStreamSynchronize(s));
-      ctx->progress(ctx->progress_user, "backward", p->n_seg - sg, p->n_seg);
+    int err = 0;
+    HIPCHK(hipMemcpyAsync(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (err) fail(MPS_EDEVICE, "a lane barrier of the batched recompute timed out");
+    for (int l = nl - 1; l >= 0; --l) {
+      const GateLane& ln = p->lanes_h[l];
+      const int g0 = ln.g0, g1 = ln.g0 + ln.ng;
+      for (int g = g1 - 1; g >= g0; --g) {
+        GateRec R = rec_at(ln.tape, L, g - g0);
+        const int* mt = meta.data() + ((size_t)l * K + (g - g0)) * 16;
+        GateDims d;
+        d.n = p->C.bond_h[g];
+        d.r = mt[0];
+        d.a = mt[4];
+        d.m = mt[5];
+        d.b = mt[6];
+        d.nu = dmeta[((size_t)l * K + (g - g0)) * 16];
+        const int n = d.n;
+        zd* Bbn = Bbar + (size_t)n * site;
+        zd* Bbn1 = Bbar + (size_t)(n + 1) * site;
+        double* lb_out = lambar + (size_t)(n + 1) * dc;
+        double* lb_in = lambar + (size_t)n * dc;
+        const int M = 2 * d.a, nb = 2 * d.b;
+        hipLaunchKernelGGL(k_adj_wbar, gemm_grid(d.r, nb), dim3(256), 0, s, R, W, (const zd*)Bbn, (const zd*)Bbn1, d, dc, gw.ldc);
+        hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, s, R, W, (const zd*)Bbn1, (const double*)lb_out, d, dc, gw.ldv);
+        hipLaunchKernelGGL(k_adj_K, gemm_grid(nb, d.r), dim3(256), 0, s, R, W, d, dc, gw.ldv);
+        hipLaunchKernelGGL(k_adj_kscale, dim3(1), dim3(256), 0, s, W, d, dc);
+        hipLaunchKernelGGL(k_adj_phi, dim3((nb * nb + 255) / 256), dim3(256), 0, s, R, W, d, dc, p->opts.broaden, gw.stats);
+        hipLaunchKernelGGL(k_adj_T, gemm_grid(M, nb), dim3(256), 0, s, R, W, d, gw.ldc);
+        hipLaunchKernelGGL(k_adj_Mbar, gemm_grid(M, nb), dim3(256), 0, s, R, W, d, gw.ldv);
+        hipLaunchKernelGGL(k_adj_Cbar, gemm_grid(M, nb), dim3(256), 0, s, R, W, (const zd*)Bbn, d, dc, gw.ldv);
+        hipLaunchKernelGGL(k_adj_lambar, dim3(d.a), dim3(256), 0, s, R, W, d, lb_in, gw.ldc);
+        const int nparts = (d.a * d.b + 255) / 256;
+        hipLaunchKernelGGL(k_adj_theta, dim3(nparts), dim3(256), 0, s, R, W, p->C.tab, g, th, d, gw.ldc);
+        hipLaunchKernelGGL(k_adj_Bl, gemm_grid(M, d.m), dim3(256), 0, s, R, W, Bbn, d, dc);
+        hipLaunchKernelGGL(k_adj_Br, gemm_grid(d.m, nb), dim3(256), 0, s, R, W, Bbn1, d, dc);
+        hipLaunchKernelGGL(k_adj_finish, dim3(1), dim3(256), 0, s, W, lb_out, dc, nparts, gphi, g, p->C.kind_h[g]);
+      }
+      HIPCHK(hipGetLastError());
+      if (ctx->progress) {
+        HIPCHK(hipStreamSynchronize(s));
+        ctx->progress(ctx->progress_user, "backward", p->n_seg - (lo + l), p->n_seg);
+      }
     }
   }
   if (!A.chain_built) build_chain(p, A);

@@ -100,6 +100,43 @@ __device__ inline void gate_matrix(const GateTable& gt, int g, const double* the
 }
 
 
+// Byte offsets of one gate record of the reverse-pass tape: the gate's inputs
+// (B_n, B_{n+1}, lambda_{n-1}), C, the orthogonalised A = C~ V, V, the singular
+// values, their order and the sizes (meta[0] = r, meta[4..6] = a, m, b;
+// dmeta[0] = nu).
+struct TapeLayout {
+  size_t oBl, oBr, olam, oC, oA, oV, osv, operm, ometa, odmeta, rec;
+};
+TapeLayout tape_layout(int dc, int ncap, int ldc, int ldv);
+
+// One lane of a batched segment recompute: gates [g0, g0 + ng) replayed on the
+// lane's own state, one tape record per gate.
+struct GateLane {
+  MpsView st;
+  int g0, ng;
+  char* tape;
+  GateStats* stats;
+  int* rotflag;       // [128] Jacobi sweep counters
+  double* nrm_part;   // [256] |C~|^2 partial sums
+  unsigned* bar;      // lane barrier counter
+  int* err;           // set when a lane barrier timed out
+};
+
+// Launch constants shared by all lanes.
+struct LaneConst {
+  GateTable gt;
+  const double* theta;
+  TapeLayout L;
+  int ldc, ldv, ncap, dmax, max_sweeps, nparts;
+  double eps, tol;
+};
+
+// Records every gate of up to nl lanes in lockstep: for step = 0 .. max ng - 1
+// the lanes' contractions, one cooperative launch of all lanes' Jacobi SVDs
+// (each lane synchronised by its own barrier) and the site updates.
+hipError_t launch_gate_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, int step, hipStream_t stream);
+int lanes_max(int dcap);
+
 // GATE_TAPE: Jacobi on C~ with the right rotations accumulated in V (the full
 // decomposition the reverse pass needs).  GATE_FWD: Jacobi on C~^H without
 // accumulation; the normalised columns are the right singular vectors.

@@ -8,6 +8,8 @@
 // is enqueued without any host synchronisation.
 #include <hip/hip_cooperative_groups.h>
 
+#include <algorithm>
+
 #include "engine.h"
 
 namespace cg = cooperative_groups;
@@ -18,9 +20,8 @@ namespace cg = cooperative_groups;
 // each thread holds the four (i, j) values of one (alpha, beta) pair.
 // C and A are column-major with leading dimension ldc; column index j'*b + beta.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int g, const double* theta,
-                                                  zd* C, zd* A, int ldc, double* nrm_part, int trans,
-                                                  int* rotflag) {
+__device__ void contract_body(const MpsView& st, const GateTable& gt, int g, const double* theta, zd* C, zd* A,
+                              int ldc, double* nrm_part, int trans, int* rotflag) {
   __shared__ zd Q[16];
   __shared__ double red[256];
   // the Jacobi kernel that follows counts rotations per sweep in rotflag
@@ -65,6 +66,12 @@ __global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int 
   }
   nrm = block_sum256(nrm, red);
   if (threadIdx.x == 0) nrm_part[part] = nrm;
+}
+
+__global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int g, const double* theta,
+                                                  zd* C, zd* A, int ldc, double* nrm_part, int trans,
+                                                  int* rotflag) {
+  contract_body(st, gt, g, theta, C, A, ldc, nrm_part, trans, rotflag);
 }
 
 // ----------------------------------------------------------------------------
@@ -190,17 +197,59 @@ __device__ inline void store_blocks(zd* dst, int ldd, const zd* src, int lsrc, i
   }
 }
 
-template <int W, bool ACC>
-__global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
+// Barrier over all work-groups of a cooperative launch (one SVD per launch).
+struct GridBarrier {
+  cg::grid_group g;
+  __device__ void sync() {
+    __threadfence();
+    g.sync();
+  }
+};
+
+// Barrier over the nblk work-groups of one lane of a batched cooperative
+// launch: a monotonic counter (zeroed before the launch) that every
+// work-group increments once per barrier; barrier k completes when it reaches
+// (k + 1) nblk.  The launch is cooperative, so every work-group of the lane is
+// resident and the wait ends; the spin is bounded all the same and a timeout
+// is recorded in *err (reported as an error by the host) instead of waiting
+// forever.
+struct LaneBarrier {
+  unsigned* ctr;
+  int* err;
+  unsigned nblk;
+  unsigned gen;
+  __device__ void sync() {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned target = (gen + 1) * nblk;
+      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned spins = 0;
+      while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        // about a second: far beyond one Jacobi round; after a timeout every
+        // later wait of the launch ends at once
+        if (++spins > (1u << 20) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      __threadfence();
+    }
+    ++gen;
+    __syncthreads();
+  }
+};
+
+template <int W, bool ACC, class Barrier>
+__device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier& bar) {
   constexpr int TPP = 256 / W;     // threads per column pair
   constexpr int RPT = 8;           // rows per thread held in registers (M, ncol <= 8 * TPP)
-  cg::grid_group grid = cg::this_grid();
   extern __shared__ zd lds[];
   const int n = s.bond;
   const int a = s.dims[n], b = s.dims[n + 2];
   const int M = s.trans ? 2 * b : 2 * a, ncol = s.trans ? 2 * a : 2 * b;
   const int P = (ncol + 2 * W - 1) / (2 * W);
-  const int p = blockIdx.x;
   const int t = threadIdx.x;
   const int mpad = s.lda;          // LDS column stride for A
   const int vpad = s.ldv;          // LDS column stride for V
@@ -334,31 +383,28 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
         store_blocks(s.A, s.lda, Al, mpad, M, ncol, W, q0, q1);
         if (ACC) store_blocks(s.V, s.ldv, Vl, vpad, ncol, ncol, W, q0, q1);
       }
-      __threadfence();
-      grid.sync();
+      bar.sync();
     }
     // Sweep finished: count the work-groups that rotated.  The counter of this
     // sweep (zeroed before the launch) is only incremented before the barrier
     // and only read after it, so every work-group reads the same value and all
     // of them leave the loop after the same number of barriers.
     if (t == 0 && sh_rot) __hip_atomic_fetch_add(&s.rotflag[sweep], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    grid.sync();
+    bar.sync();
     if (t == 0) sh_stop = __hip_atomic_load(&s.rotflag[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     __syncthreads();
     if (sh_stop) break;
   }
   const int used = sweep + 1;
   // singular values: column norms
-  for (int c = p; c < ncol; c += gridDim.x) {
+  for (int c = p; c < ncol; c += nblk) {
     double acc = 0.0;
     for (int r = t; r < M; r += 256) acc += zabs2(s.A[(size_t)c * s.lda + r]);
     __shared__ double red[256];
     acc = block_sum256(acc, red);
     if (t == 0) s.sv[c] = sqrt(acc);
   }
-  __threadfence();
-  grid.sync();
+  bar.sync();
   if (p != 0) return;
   // work-group 0: order, rank, normalisation, lambda, statistics
   __shared__ double shs[1024];
@@ -416,12 +462,17 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
   for (int q = t; q < r; q += 256) s.lam_out[q] = shs[s.perm[q]] / nu;
 }
 
+template <int W, bool ACC>
+__global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
+  GridBarrier bar{cg::this_grid()};
+  svd_body<W, ACC>(s, blockIdx.x, gridDim.x, bar);
+}
+
 // ----------------------------------------------------------------------------
 // k_update_left: B~_n[(a,i'), mu] = sum_c C[(a,i'), c] V[c, perm[mu]] / nu.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_update_left(MpsView st, int n, const zd* C, int ldc, const zd* V,
-                                                     int ldv, const int* perm, const int* gmeta,
-                                                     const double* gdmeta) {
+__device__ void update_left_body(const MpsView& st, int n, const zd* C, int ldc, const zd* V, int ldv,
+                                 const int* perm, const int* gmeta, const double* gdmeta) {
   const int a = st.dims[n], b = st.dims[n + 2];
   const int r = gmeta[0];
   const double inv = 1.0 / gdmeta[0];
@@ -442,9 +493,15 @@ __global__ __launch_bounds__(256) void k_update_left(MpsView st, int n, const zd
     }
 }
 
+__global__ __launch_bounds__(256) void k_update_left(MpsView st, int n, const zd* C, int ldc, const zd* V,
+                                                     int ldv, const int* perm, const int* gmeta,
+                                                     const double* gdmeta) {
+  update_left_body(st, n, C, ldc, V, ldv, perm, gmeta, gdmeta);
+}
+
 // k_update_right: B~_{n+1}[mu, j', beta] = conj(V[j'*b + beta, perm[mu]]).
-__global__ __launch_bounds__(256) void k_update_right(MpsView st, int n, const zd* V, int ldv, const int* perm,
-                                                      const int* gmeta) {
+__device__ void update_right_body(const MpsView& st, int n, const zd* V, int ldv, const int* perm,
+                                  const int* gmeta) {
   const int b = st.dims[n + 2];
   const int r = gmeta[0];
   const int mu = blockIdx.x;
@@ -456,6 +513,11 @@ __global__ __launch_bounds__(256) void k_update_right(MpsView st, int n, const z
     const int jp = e / b, be = e % b;
     Br[(size_t)mu * 2 * dc + jp * dc + be] = zconj(V[(size_t)col * ldv + e]);
   }
+}
+
+__global__ __launch_bounds__(256) void k_update_right(MpsView st, int n, const zd* V, int ldv, const int* perm,
+                                                      const int* gmeta) {
+  update_right_body(st, n, V, ldv, perm, gmeta);
 }
 
 // Forward mode (Jacobi on X = C~^H, no accumulation): column c of the rotated
@@ -503,6 +565,179 @@ __global__ __launch_bounds__(256) void k_update_right_t(MpsView st, int n, const
     const int jp = e / b, be = e % b;
     Br[(size_t)mu * 2 * dc + jp * dc + be] = zscale(zconj(X[(size_t)col * ldc + e]), inv);
   }
+}
+
+// ----------------------------------------------------------------------------
+// Batched segment recompute: lane kernels.  Lane l replays gate g0 + step of its
+// segment on its own state and writes the gate's tape record.
+// ----------------------------------------------------------------------------
+struct LaneRec {
+  zd *Bl, *Br, *C, *A, *V;
+  double *lam, *sv, *dmeta;
+  int *perm, *meta;
+};
+
+__device__ inline LaneRec lane_rec(const GateLane& ln, const TapeLayout& L, int step) {
+  char* r = ln.tape + (size_t)step * L.rec;
+  LaneRec R;
+  R.Bl = (zd*)(r + L.oBl);
+  R.Br = (zd*)(r + L.oBr);
+  R.lam = (double*)(r + L.olam);
+  R.C = (zd*)(r + L.oC);
+  R.A = (zd*)(r + L.oA);
+  R.V = (zd*)(r + L.oV);
+  R.sv = (double*)(r + L.osv);
+  R.perm = (int*)(r + L.operm);
+  R.meta = (int*)(r + L.ometa);
+  R.dmeta = (double*)(r + L.odmeta);
+  return R;
+}
+
+// Gate inputs into the tape: B_n, B_{n+1}, lambda_{n-1} and the sizes (a, m, b).
+__global__ __launch_bounds__(256) void k_tape_inputs_lanes(const GateLane* lanes, LaneConst c, int step) {
+  const GateLane& ln = lanes[blockIdx.y];
+  if (step >= ln.ng) return;
+  const int n = c.gt.bond[ln.g0 + step];
+  const LaneRec R = lane_rec(ln, c.L, step);
+  const MpsView& st = ln.st;
+  const int a = st.dims[n], m = st.dims[n + 1], b = st.dims[n + 2];
+  const int dc = st.dcap;
+  const size_t site = (size_t)dc * 2 * dc;
+  const zd* s0 = st.site(n);
+  const zd* s1 = st.site(n + 1);
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < site; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e / dc), col = (int)(e % dc);
+    const int l = row >> 1;
+    if (l < a && col < m) R.Bl[e] = s0[e];
+    if (l < m && col < b) R.Br[e] = s1[e];
+  }
+  if (blockIdx.x == 0) {
+    for (int q = threadIdx.x; q < a; q += blockDim.x) R.lam[q] = st.lam[(size_t)n * dc + q];
+    if (threadIdx.x == 0) {
+      R.meta[4] = a;
+      R.meta[5] = m;
+      R.meta[6] = b;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_contract_lanes(const GateLane* lanes, LaneConst c, int step) {
+  const GateLane& ln = lanes[blockIdx.z];
+  if (step >= ln.ng) return;
+  // the lane's barrier counter starts from zero in the SVD launch that follows
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ln.bar = 0u;
+  const LaneRec R = lane_rec(ln, c.L, step);
+  contract_body(ln.st, c.gt, ln.g0 + step, c.theta, R.C, R.A, c.ldc, ln.nrm_part, 0, ln.rotflag);
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_svd_jacobi_lanes(const GateLane* lanes, LaneConst c, int step, int nblk) {
+  const int lane = blockIdx.x / nblk, p = blockIdx.x % nblk;
+  const GateLane& ln = lanes[lane];
+  if (step >= ln.ng) return;     // uniform over the lane's work-groups
+  const int n = c.gt.bond[ln.g0 + step];
+  const LaneRec R = lane_rec(ln, c.L, step);
+  SvdArgs s;
+  s.A = R.A;
+  s.lda = c.ldc;
+  s.V = R.V;
+  s.ldv = c.ldv;
+  s.dims = ln.st.dims;
+  s.bond = n;
+  s.sv = R.sv;
+  s.perm = R.perm;
+  s.gmeta = R.meta;
+  s.gdmeta = R.dmeta;
+  s.rotflag = ln.rotflag;
+  s.lam_out = ln.st.lam + (size_t)(n + 1) * ln.st.dcap;
+  s.stats = ln.stats;
+  s.eps = c.eps;
+  s.dmax = c.dmax;
+  s.tol = c.tol;
+  s.max_sweeps = c.max_sweeps;
+  s.nrm_part = ln.nrm_part;
+  s.nparts = c.nparts;
+  s.trans = 0;
+  LaneBarrier bar{ln.bar, ln.err, (unsigned)nblk, 0u};
+  svd_body<W, true>(s, p, nblk, bar);
+}
+
+__global__ __launch_bounds__(256) void k_update_left_lanes(const GateLane* lanes, LaneConst c, int step) {
+  const GateLane& ln = lanes[blockIdx.z];
+  if (step >= ln.ng) return;
+  const LaneRec R = lane_rec(ln, c.L, step);
+  update_left_body(ln.st, c.gt.bond[ln.g0 + step], R.C, c.ldc, R.V, c.ldv, R.perm, R.meta, R.dmeta);
+}
+
+__global__ __launch_bounds__(256) void k_update_right_lanes(const GateLane* lanes, LaneConst c, int step) {
+  const GateLane& ln = lanes[blockIdx.y];
+  if (step >= ln.ng) return;
+  const LaneRec R = lane_rec(ln, c.L, step);
+  update_right_body(ln.st, c.gt.bond[ln.g0 + step], R.V, c.ldv, R.perm, R.meta);
+}
+
+static const void* svd_lane_kernel(int W) {
+  switch (W) {
+    case 32: return (const void*)k_svd_jacobi_lanes<32>;
+    case 16: return (const void*)k_svd_jacobi_lanes<16>;
+    case 8: return (const void*)k_svd_jacobi_lanes<8>;
+    default: return (const void*)k_svd_jacobi_lanes<4>;
+  }
+}
+
+TapeLayout tape_layout(int dc, int ncap, int ldc, int ldv) {
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  TapeLayout L;
+  size_t o = 0;
+  const size_t site = (size_t)dc * 2 * dc * sizeof(zd);
+  L.oBl = o; o = al(o + site);
+  L.oBr = o; o = al(o + site);
+  L.olam = o; o = al(o + dc * sizeof(double));
+  L.oC = o; o = al(o + (size_t)ncap * ldc * sizeof(zd));
+  L.oA = o; o = al(o + (size_t)ncap * ldc * sizeof(zd));
+  L.oV = o; o = al(o + (size_t)ncap * ldv * sizeof(zd));
+  L.osv = o; o = al(o + ncap * sizeof(double));
+  L.operm = o; o = al(o + ncap * sizeof(int));
+  L.ometa = o; o = al(o + 16 * sizeof(int));
+  L.odmeta = o; o = al(o + 16 * sizeof(double));
+  L.rec = o;
+  return L;
+}
+
+// Lanes that fit one cooperative launch: the SVD kernel holds one work-group
+// per compute unit (its LDS use), each lane needs P of them.
+int lanes_max(int dcap) {
+  const int W = svd_width(dcap);
+  const int P = (2 * dcap + 2 * W - 1) / (2 * W);
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+  const size_t shm = svd_shared_bytes(dcap, 2 * dcap, 2 * P * W, GATE_TAPE);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, svd_lane_kernel(W), 256, shm) != hipSuccess) return 1;
+  return std::max(1, per_cu * cus / P);
+}
+
+hipError_t launch_gate_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, int step, hipStream_t stream) {
+  const int dc = c.ldc / 2;
+  const int tiles = (c.ldc + ZT_M - 1) / ZT_M;
+  hipLaunchKernelGGL(k_tape_inputs_lanes, dim3(64, nl), dim3(256), 0, stream, d_lanes, c, step);
+  hipLaunchKernelGGL(k_contract_lanes, dim3(tiles, tiles, nl), dim3(256), 0, stream, d_lanes, c, step);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int W = svd_width(dc);
+  const int P = (c.ncap + 2 * W - 1) / (2 * W);
+  const size_t shm = svd_shared_bytes(dc, c.ldc, c.ldv, GATE_TAPE);
+  e = hipFuncSetAttribute(svd_lane_kernel(W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  LaneConst cc = c;
+  int stp = step, nb = P;
+  void* args[] = {(void*)&d_lanes, &cc, &stp, &nb};
+  e = hipLaunchCooperativeKernel(svd_lane_kernel(W), dim3(P * nl), dim3(256), args, shm, stream);
+  if (e != hipSuccess) return e;
+  const int tm = (2 * dc + ZT_M - 1) / ZT_M, tn = (dc + ZT_N - 1) / ZT_N;
+  hipLaunchKernelGGL(k_update_left_lanes, dim3(tn, tm, nl), dim3(256), 0, stream, d_lanes, c, step);
+  hipLaunchKernelGGL(k_update_right_lanes, dim3(dc, nl), dim3(256), 0, stream, d_lanes, c, step);
+  return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------

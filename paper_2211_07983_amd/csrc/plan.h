@@ -97,7 +97,10 @@ struct mps_plan {
   mps_grad_opts opts{256, 0.0, 64, 0};
   std::vector<uint8_t> occ_h;
   mps_state* state = nullptr;      // working state
-  mps_state* replay = nullptr;     // state used to recompute a segment
+  std::vector<mps_state*> replays; // one state per lane of the batched segment recompute
+  std::vector<GateLane> lanes_h;   // host copy of the lane table
+  DevBuf lanes_dev;                // device lane table
+  DevBuf lane_aux;                 // per-lane counters, partial sums, stats, barrier words
   DevCircuit C;
   DevHamiltonian H;
   DevBuf theta, grad, gphi;
@@ -107,7 +110,7 @@ struct mps_plan {
   double E = 0.0, Z = 1.0, Eim = 0.0;
   // reverse pass
   DevBuf Bbar, lambar;             // cotangents of the site tensors and Schmidt vectors
-  DevBuf tape;                     // per-gate records of one segment
+  DevBuf tape;                     // per-gate records of the segments recomputed together
   DevBuf work;                     // per-gate adjoint workspace
   DevBuf sweep_work;               // sweep-adjoint buffers
   void* adj = nullptr;             // reverse-pass state (adjoint.hip)

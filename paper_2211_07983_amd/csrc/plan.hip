@@ -17,7 +17,7 @@ void plan_adj_free(void* a);
 
 mps_plan::~mps_plan() {
   delete state;
-  delete replay;
+  for (mps_state* r : replays) delete r;
   plan_adj_free(adj);
 }
 
@@ -158,7 +158,6 @@ mps_status mps_plan_create(mps_ctx* ctx, const uint8_t* occ_bits, const mps_circ
       p->n_theta = nth;
       p->occ_h.assign(occ_bits, occ_bits + N);
       p->state = plan_new_state(ctx, N, *trunc, occ_bits);
-      p->replay = plan_new_state(ctx, N, *trunc, nullptr);
       p->C.upload_from(circuit, ctx->stream);
       p->H.upload_from(h, N, p->state->dcap, ctx->stream, ctx->sweep_budget);
       HIPCHK(hipStreamSynchronize(ctx->stream));
