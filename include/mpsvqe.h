@@ -176,6 +176,25 @@ mps_status mps_energy_grad(mps_plan* plan, const double* theta, int32_t n_theta,
                            int32_t theta_on_device, double* energy, double* grad,
                            mps_stats* stats);
 
+/* Batched form of mps_energy_grad: energies[b] and grads[b][:] of n_batch
+ * parameter vectors thetas[b][:] of the same plan (row-major [n_batch][n_theta];
+ * host arrays, or device addresses for thetas and grads when
+ * theta_on_device != 0; energies is always host).  The vectors go through the
+ * circuit together: each gate step is one launch per kernel for all of them
+ * (as many as fit the device at once; larger batches run in groups), so the
+ * compute units that a single evaluation's SVD chain leaves idle are used.
+ * Every result equals the one of mps_energy_grad on that vector alone.
+ * stats: sums over the batch (truncation, bonds, sweeps) and the wall time of
+ * the whole call in t_backward_ms.                                          */
+mps_status mps_energy_grad_batched(mps_plan* plan, int32_t n_batch, const double* thetas, int32_t n_theta,
+                                   int32_t theta_on_device, double* energies, double* grads,
+                                   mps_stats* stats);
+
+/* Parameter vectors that one batched launch holds for this plan (the SVD of
+ * each vector occupies ceil(2 d_max / (2 W)) compute units); larger batches
+ * run in groups of this size.  Returns <= 0 on error.                      */
+int32_t mps_plan_batch_width(mps_plan* plan);
+
 /* Forward pass of a plan only (energy at theta, no gradient).              */
 mps_status mps_plan_energy(mps_plan* plan, const double* theta, int32_t n_theta,
                            double* energy, mps_stats* stats);

@@ -247,6 +247,38 @@ class Plan:
                                                      C.byref(e), g.ctypes.data_as(C.c_void_p), C.byref(s)))
         return e.value, g, s.as_dict()
 
+    def lanes_per_launch(self):
+        """Parameter vectors one batched launch holds (mps_plan_batch_width)."""
+        w = self.ctx._lib.mps_plan_batch_width(self.h)
+        if w <= 0:
+            self.ctx.check(w)
+        return w
+
+    def energy_grad_batched(self, thetas):
+        """thetas: [n_batch, n_theta] numpy array or device torch tensor; returns
+        (energies [n_batch], grads [n_batch, n_theta], stats)."""
+        s = Stats()
+        if hasattr(thetas, "is_cuda") and thetas.is_cuda:
+            import torch
+            th = thetas.detach().to(torch.float64).contiguous()
+            nb = th.shape[0]
+            e = np.zeros(nb)
+            g = torch.empty_like(th)
+            self.ctx.check(self.ctx._lib.mps_energy_grad_batched(
+                self.h, nb, C.c_void_p(th.data_ptr()), th.shape[1], 1, _ptr(e, C.c_double), C.c_void_p(g.data_ptr()),
+                C.byref(s)))
+            return e, g, s.as_dict()
+        th = np.ascontiguousarray(thetas, dtype=np.float64)
+        if th.ndim != 2:
+            raise ValueError("thetas must be [n_batch, n_theta]")
+        nb = th.shape[0]
+        e = np.zeros(nb)
+        g = np.zeros_like(th)
+        self.ctx.check(self.ctx._lib.mps_energy_grad_batched(
+            self.h, nb, th.ctypes.data_as(C.c_void_p), th.shape[1], 0, _ptr(e, C.c_double),
+            g.ctypes.data_as(C.c_void_p), C.byref(s)))
+        return e, g, s.as_dict()
+
     def free(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             self.ctx._lib.mps_plan_free(self.h)

@@ -227,9 +227,29 @@ struct GateDims {
   double nu;
 };
 
+// One lane of a batched gate adjoint: the gate's tape record, a workspace and
+// the cotangent buffers of the evaluation it belongs to.  Launches cover nl
+// lanes with blockIdx.z = lane; grids are sized for the largest lane.
+struct AdjLane {
+  GateRec R;
+  AdjWork W;
+  GateDims d;
+  zd* Bbn;            // Bbar_n of this evaluation
+  zd* Bbn1;           // Bbar_{n+1}
+  double* lb_out;     // lambar_{n} (bond of the gate, read then cleared)
+  double* lb_in;      // lambar_{n-1} (accumulated)
+  double* gphi;       // [G] dE/dphi of this evaluation
+  const double* theta;
+};
+
 // A1: Wbar[mu, c] = sum_row conj(Bbar_n[row, mu]) / nu * C[row, c] + Bbar_{n+1}[mu, c]
-__global__ __launch_bounds__(256) void k_adj_wbar(GateRec R, AdjWork W, const zd* Bbn, const zd* Bbn1, GateDims d,
-                                                  int dc, int ldc) {
+__global__ __launch_bounds__(256) void k_adj_wbar(const AdjLane* AL, int dc, int ldc) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
+  const zd* Bbn = ln.Bbn;
+  const zd* Bbn1 = ln.Bbn1;
   const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
   if (i0 >= d.r || j0 >= 2 * d.b) return;
   const double inv = 1.0 / d.nu;
@@ -251,8 +271,13 @@ __global__ __launch_bounds__(256) void k_adj_wbar(GateRec R, AdjWork W, const zd
 }
 
 // A2: nu_bar and s_bar of the kept values (one block)
-__global__ __launch_bounds__(256) void k_adj_scalars(GateRec R, AdjWork W, const zd* Bbn1, const double* lbar_out,
-                                                     GateDims d, int dc, int ldv) {
+__global__ __launch_bounds__(256) void k_adj_scalars(const AdjLane* AL, int dc, int ldv) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
+  const zd* Bbn1 = ln.Bbn1;
+  const double* lbar_out = ln.lb_out;
   __shared__ double red[256];
   const int t = threadIdx.x;
   double d1 = 0.0;
@@ -273,7 +298,11 @@ __global__ __launch_bounds__(256) void k_adj_scalars(GateRec R, AdjWork W, const
 }
 
 // A3: Kt[i, mu] = sum_c conj(P[c, i]) conj(Wbar[mu, c]),  P = V[:, perm]
-__global__ __launch_bounds__(256) void k_adj_K(GateRec R, AdjWork W, GateDims d, int dc, int ldv) {
+__global__ __launch_bounds__(256) void k_adj_K(const AdjLane* AL, int dc, int ldv) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
   const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
   const int nb = 2 * d.b;
   if (i0 >= nb || j0 >= d.r) return;
@@ -290,7 +319,10 @@ __global__ __launch_bounds__(256) void k_adj_K(GateRec R, AdjWork W, GateDims d,
 }
 
 // A4: kscale = max |Kt| (one block, deterministic)
-__global__ __launch_bounds__(256) void k_adj_kscale(AdjWork W, GateDims d, int dc) {
+__global__ __launch_bounds__(256) void k_adj_kscale(const AdjLane* AL, int dc) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
   __shared__ double red[256];
   const int t = threadIdx.x;
   double m = 0.0;
@@ -308,7 +340,11 @@ __global__ __launch_bounds__(256) void k_adj_kscale(AdjWork W, GateDims d, int d
 }
 
 // A5: Phi (sorted basis), Gamma_ij / s_i of the complex SVD adjoint
-__global__ void k_adj_phi(GateRec R, AdjWork W, GateDims d, int dc, double eta, GateStats* st) {
+__global__ void k_adj_phi(const AdjLane* AL, int dc, double eta, GateStats* st) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
   const int nb = 2 * d.b;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nb * nb) return;
@@ -339,7 +375,11 @@ __global__ void k_adj_phi(GateRec R, AdjWork W, GateDims d, int dc, double eta, 
 }
 
 // A6: T[row, j] = sum_i A[row, perm i] Phi[i, j]
-__global__ __launch_bounds__(256) void k_adj_T(GateRec R, AdjWork W, GateDims d, int ldc) {
+__global__ __launch_bounds__(256) void k_adj_T(const AdjLane* AL, int ldc) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
   const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
   const int M = 2 * d.a, nb = 2 * d.b;
   if (i0 >= M || j0 >= nb) return;
@@ -354,7 +394,11 @@ __global__ __launch_bounds__(256) void k_adj_T(GateRec R, AdjWork W, GateDims d,
 }
 
 // A7: Mbar[row, c] = sum_j T[row, j] conj(P[c, j])
-__global__ __launch_bounds__(256) void k_adj_Mbar(GateRec R, AdjWork W, GateDims d, int ldv) {
+__global__ __launch_bounds__(256) void k_adj_Mbar(const AdjLane* AL, int ldv) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
   const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
   const int M = 2 * d.a, nb = 2 * d.b;
   if (i0 >= M || j0 >= nb) return;
@@ -369,7 +413,12 @@ __global__ __launch_bounds__(256) void k_adj_Mbar(GateRec R, AdjWork W, GateDims
 }
 
 // A8: Cbar[row, c] = sum_mu Bbar_n[row, mu]/nu conj(P[c, mu]) + lambda_in[alpha] Mbar[row, c]
-__global__ __launch_bounds__(256) void k_adj_Cbar(GateRec R, AdjWork W, const zd* Bbn, GateDims d, int dc, int ldv) {
+__global__ __launch_bounds__(256) void k_adj_Cbar(const AdjLane* AL, int dc, int ldv) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
+  const zd* Bbn = ln.Bbn;
   const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
   const int M = 2 * d.a, nb = 2 * d.b;
   if (i0 >= M || j0 >= nb) return;
@@ -392,9 +441,15 @@ __global__ __launch_bounds__(256) void k_adj_Cbar(GateRec R, AdjWork W, const zd
 }
 
 // A9: lambar_{n-1}[alpha] += Re sum conj(Mbar[(alpha,i'), c]) C[(alpha,i'), c]
-__global__ __launch_bounds__(256) void k_adj_lambar(GateRec R, AdjWork W, GateDims d, double* lbar_in, int ldc) {
+__global__ __launch_bounds__(256) void k_adj_lambar(const AdjLane* AL, int ldc) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
+  double* lbar_in = ln.lb_in;
   __shared__ double red[256];
   const int al = blockIdx.x;
+  if (al >= d.a) return;
   const int nb = 2 * d.b;
   double s = 0.0;
   for (int e = threadIdx.x; e < 2 * nb; e += 256) {
@@ -408,8 +463,12 @@ __global__ __launch_bounds__(256) void k_adj_lambar(GateRec R, AdjWork W, GateDi
 }
 
 // A10: Theta_bar = Q^dagger C_bar on (i', j'); dphi partial sums Re <C_bar, D C>
-__global__ __launch_bounds__(256) void k_adj_theta(GateRec R, AdjWork W, GateTable gt, int g, const double* theta,
-                                                   GateDims d, int ldc) {
+__global__ __launch_bounds__(256) void k_adj_theta(const AdjLane* AL, GateTable gt, int g, int ldc) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
+  const double* theta = ln.theta;
   __shared__ zd Q[16];
   __shared__ zd D[16];
   __shared__ double red[256];
@@ -457,7 +516,12 @@ __global__ __launch_bounds__(256) void k_adj_theta(GateRec R, AdjWork W, GateTab
 }
 
 // A11: Bbar_n[(alpha,i), gamma] = sum_c Theta_bar[(alpha,i), c] conj(B_{n+1}[gamma, c])
-__global__ __launch_bounds__(256) void k_adj_Bl(GateRec R, AdjWork W, zd* Bbn, GateDims d, int dc) {
+__global__ __launch_bounds__(256) void k_adj_Bl(const AdjLane* AL, int dc) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
+  zd* Bbn = ln.Bbn;
   const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
   const int M = 2 * d.a;
   if (i0 >= M || j0 >= d.m) return;
@@ -477,7 +541,12 @@ __global__ __launch_bounds__(256) void k_adj_Bl(GateRec R, AdjWork W, zd* Bbn, G
 }
 
 // A12: Bbar_{n+1}[gamma, c] = sum_row conj(B_n[row, gamma]) Theta_bar[row, c]
-__global__ __launch_bounds__(256) void k_adj_Br(GateRec R, AdjWork W, zd* Bbn1, GateDims d, int dc) {
+__global__ __launch_bounds__(256) void k_adj_Br(const AdjLane* AL, int dc) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const GateRec& R = ln.R;
+  const AdjWork& W = ln.W;
+  const GateDims& d = ln.d;
+  zd* Bbn1 = ln.Bbn1;
   const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
   const int nb = 2 * d.b;
   if (i0 >= d.m || j0 >= nb) return;
@@ -497,7 +566,11 @@ __global__ __launch_bounds__(256) void k_adj_Br(GateRec R, AdjWork W, zd* Bbn1, 
 }
 
 // A13: lambar_n = 0 (the old lambda_n was overwritten by this gate); dE/dphi
-__global__ void k_adj_finish(AdjWork W, double* lbar_out, int dc, int nparts, double* gphi, int g, int param) {
+__global__ void k_adj_finish(const AdjLane* AL, int dc, int nparts, int g, int param) {
+  const AdjLane& ln = AL[blockIdx.z];
+  const AdjWork& W = ln.W;
+  double* lbar_out = ln.lb_out;
+  double* gphi = ln.gphi;
   for (int q = threadIdx.x; q < dc; q += blockDim.x) lbar_out[q] = 0.0;
   if (threadIdx.x == 0 && param) {
     double s = 0.0;
@@ -547,10 +620,13 @@ struct SweepAdjPlan {
   int chunk_slots = 0;
 };
 
+struct BatchSet;
 struct PlanAdj {
   SweepAdjPlan sw;
   DevBuf chain_start, chain_list;
   bool chain_built = false;
+  BatchSet* batch = nullptr;   // lanes of the batched form (allocated on first use)
+  ~PlanAdj();
 };
 
 static PlanAdj& adj_of(mps_plan* p) {
@@ -714,17 +790,19 @@ static void build_sweep_adjoint(mps_plan* p, SweepAdjPlan& S, const std::vector<
   S.built = true;
 }
 
-static void run_sweep_adjoint(mps_plan* p, const std::vector<int>& dims) {
+// Site cotangents of E = c0 + sum_k c_k <P_k> / Z for the state st (final
+// bond dims `dims`, energy E, norm Z) into Bbar.
+static void run_sweep_adjoint(mps_plan* p, const std::vector<int>& dims, const mps_state* st, zd* Bbar, double E,
+                              double Z) {
   mps_ctx* ctx = p->ctx;
   hipStream_t s = ctx->stream;
   SweepAdjPlan& S = adj_of(p).sw;
   if (!S.built || S.dims != dims || S.lid != ctx->sb.Lid || S.rid != ctx->sb.Rid) build_sweep_adjoint(p, S, dims);
   const int N = p->N, dc = S.dc;
   const size_t dd = (size_t)dc * dc;
-  zd* Bbar = (zd*)p->Bbar.p;
   zd* Lagg = (zd*)S.Lagg.p;
   zd* Ragg = (zd*)S.Ragg.p;
-  const zd* B = (const zd*)p->state->B.p;
+  const zd* B = (const zd*)st->B.p;
   const size_t site = (size_t)dc * 2 * dc;
   HIPCHK(hipMemsetAsync(Bbar, 0, (size_t)N * site * sizeof(zd), s));
   HIPCHK(hipMemsetAsync(Lagg, 0, (size_t)(N + 1) * dd * sizeof(zd), s));
@@ -797,7 +875,7 @@ static void run_sweep_adjoint(mps_plan* p, const std::vector<int>& dims) {
     hipLaunchKernelGGL(k_env_right2, gemm_grid(a, a), dim3(256), 0, s, dj, B + (size_t)m * site, a, b, dc);
     HIPCHK(hipStreamSynchronize(s));
   }
-  const double zc = -(p->E - p->H.c0);
+  const double zc = -(E - p->H.c0);
   for (int n = 0; n < N; ++n) {
     const int a = dims[n], b = dims[n + 1];
     const zd* Bn = B + (size_t)n * site;
@@ -819,8 +897,8 @@ static void run_sweep_adjoint(mps_plan* p, const std::vector<int>& dims) {
     hipLaunchKernelGGL(k_env_reduce, dim3((a * 2 * b + 255) / 256), dim3(256), 0, s, dj, 3, Bbar + (size_t)n * site, a, b, dc);
     HIPCHK(hipStreamSynchronize(s));
   }
-  hipLaunchKernelGGL(k_scale_sites, dim3(64, N), dim3(256), 0, s, Bbar, (const int*)p->state->dims.p, N, dc,
-                     2.0 / p->Z);
+  hipLaunchKernelGGL(k_scale_sites, dim3(64, N), dim3(256), 0, s, Bbar, (const int*)st->dims.p, N, dc,
+                     2.0 / Z);
   HIPCHK(hipGetLastError());
 }
 
@@ -860,6 +938,63 @@ static void build_chain(mps_plan* p, PlanAdj& A) {
   A.chain_built = true;
 }
 
+// Workspace of one lane of the gate adjoint.
+static size_t adjwork_layout(int ncap, int dc, AdjWork* W, char* w) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = al256(o + bytes); return r; };
+  const size_t zm = (size_t)ncap * ncap * sizeof(zd);
+  const size_t oW = take(zm), oK = take((size_t)ncap * dc * sizeof(zd)), oP = take(zm), oT = take(zm),
+               oM = take(zm), oCb = take(zm), oTh = take(zm), oS = take(dc * sizeof(double)),
+               oSc = take(8 * sizeof(double)), oD = take(1024 * sizeof(double));
+  if (W) {
+    W->Wbar = (zd*)(w + oW);
+    W->Kt = (zd*)(w + oK);
+    W->Phi = (zd*)(w + oP);
+    W->T = (zd*)(w + oT);
+    W->Mbar = (zd*)(w + oM);
+    W->Cbar = (zd*)(w + oCb);
+    W->Thb = (zd*)(w + oTh);
+    W->sbar = (double*)(w + oS);
+    W->scal = (double*)(w + oSc);
+    W->dpart = (double*)(w + oD);
+    W->ldw = ncap;
+  }
+  return al256(o);
+}
+
+// The adjoint of one gate (A1..A13) for nl lanes; mx holds the largest sizes
+// over the lanes, which set the grids.
+static void launch_gate_adjoint(const AdjLane* al, int nl, const GateDims& mx, int g, int param_kind,
+                                const GateTable& gt, int dc, const GateWork& gw, double eta, hipStream_t s) {
+  const int M = 2 * mx.a, nb = 2 * mx.b;
+  hipLaunchKernelGGL(k_adj_wbar, gemm_grid(mx.r, nb, nl), dim3(256), 0, s, al, dc, gw.ldc);
+  hipLaunchKernelGGL(k_adj_scalars, dim3(1, 1, nl), dim3(256), 0, s, al, dc, gw.ldv);
+  hipLaunchKernelGGL(k_adj_K, gemm_grid(nb, mx.r, nl), dim3(256), 0, s, al, dc, gw.ldv);
+  hipLaunchKernelGGL(k_adj_kscale, dim3(1, 1, nl), dim3(256), 0, s, al, dc);
+  hipLaunchKernelGGL(k_adj_phi, dim3((nb * nb + 255) / 256, 1, nl), dim3(256), 0, s, al, dc, eta, gw.stats);
+  hipLaunchKernelGGL(k_adj_T, gemm_grid(M, nb, nl), dim3(256), 0, s, al, gw.ldc);
+  hipLaunchKernelGGL(k_adj_Mbar, gemm_grid(M, nb, nl), dim3(256), 0, s, al, gw.ldv);
+  hipLaunchKernelGGL(k_adj_Cbar, gemm_grid(M, nb, nl), dim3(256), 0, s, al, dc, gw.ldv);
+  hipLaunchKernelGGL(k_adj_lambar, dim3(mx.a, 1, nl), dim3(256), 0, s, al, gw.ldc);
+  const int nparts = (mx.a * mx.b + 255) / 256;
+  hipLaunchKernelGGL(k_adj_theta, dim3(nparts, 1, nl), dim3(256), 0, s, al, gt, g, gw.ldc);
+  hipLaunchKernelGGL(k_adj_Bl, gemm_grid(M, mx.m, nl), dim3(256), 0, s, al, dc);
+  hipLaunchKernelGGL(k_adj_Br, gemm_grid(mx.m, nb, nl), dim3(256), 0, s, al, dc);
+  hipLaunchKernelGGL(k_adj_finish, dim3(1, 1, nl), dim3(256), 0, s, al, dc, nparts, g, param_kind);
+}
+
+// Sizes of a recorded gate (from the tape's meta fields read back to the host).
+static GateDims dims_of(const int* mt, const double* dmt, int n) {
+  GateDims d;
+  d.n = n;
+  d.r = mt[0];
+  d.a = mt[4];
+  d.m = mt[5];
+  d.b = mt[6];
+  d.nu = dmt[0];
+  return d;
+}
+
 void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   mps_ctx* ctx = p->ctx;
   hipStream_t s = ctx->stream;
@@ -878,7 +1013,7 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   p->Bbar.ensure((size_t)N * site * sizeof(zd));
   p->lambar.ensure((size_t)(N + 1) * dc * sizeof(double));
   HIPCHK(hipMemsetAsync(p->lambar.p, 0, p->lambar.bytes, s));
-  run_sweep_adjoint(p, dims);
+  run_sweep_adjoint(p, dims, st, (zd*)p->Bbar.p, p->E, p->Z);
   // ---- gate adjoint
   GateWork gw = ctx->gw;
   const TapeLayout L = tape_layout(dc, gw.ncap, gw.ldc, gw.ldv);
@@ -899,7 +1034,6 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   p->lanes_h.resize(nlanes);
   LaneConst lc;
   lc.gt = p->C.tab;
-  lc.theta = (const double*)p->theta.p;
   lc.L = L;
   lc.ldc = gw.ldc;
   lc.ldv = gw.ldv;
@@ -909,28 +1043,8 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   lc.nparts = ((2 * dc + ZT_M - 1) / ZT_M) * ((2 * dc + ZT_M - 1) / ZT_M);
   lc.eps = gw.eps;
   lc.tol = gw.tol;
-  const int ldw = gw.ncap;
   AdjWork W;
-  {
-    size_t o = 0;
-    auto take = [&](size_t bytes) { size_t r = o; o = al256(o + bytes); return r; };
-    const size_t zm = (size_t)gw.ncap * ldw * sizeof(zd);
-    const size_t oW = take(zm), oK = take((size_t)gw.ncap * dc * sizeof(zd)), oP = take(zm), oT = take(zm),
-                 oM = take(zm), oCb = take(zm), oTh = take(zm), oS = take(dc * sizeof(double)),
-                 oSc = take(8 * sizeof(double)), oD = take(1024 * sizeof(double));
-    char* w = (char*)p->work.ensure(o);
-    W.Wbar = (zd*)(w + oW);
-    W.Kt = (zd*)(w + oK);
-    W.Phi = (zd*)(w + oP);
-    W.T = (zd*)(w + oT);
-    W.Mbar = (zd*)(w + oM);
-    W.Cbar = (zd*)(w + oCb);
-    W.Thb = (zd*)(w + oTh);
-    W.sbar = (double*)(w + oS);
-    W.scal = (double*)(w + oSc);
-    W.dpart = (double*)(w + oD);
-    W.ldw = ldw;
-  }
+  adjwork_layout(gw.ncap, dc, &W, (char*)p->work.ensure(adjwork_layout(gw.ncap, dc, nullptr, nullptr)));
   double* gphi = (double*)p->gphi.ensure((size_t)std::max(1, p->C.G) * sizeof(double));
   HIPCHK(hipMemsetAsync(gphi, 0, p->gphi.bytes, s));
   zd* Bbar = (zd*)p->Bbar.p;
@@ -938,6 +1052,8 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   const double* th = (const double*)p->theta.p;
   std::vector<int> meta((size_t)nlanes * K * 16);
   std::vector<double> dmeta((size_t)nlanes * K * 16);
+  std::vector<AdjLane> rec;      // lives until the final synchronisation below
+  std::vector<GateDims> dd;
   for (int hi = p->n_seg - 1; hi >= 0; hi -= nlanes) {
     const int lo = std::max(0, hi - nlanes + 1), nl = hi - lo + 1;
     int steps = 0;
@@ -949,6 +1065,8 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
       ln.st = view_of(rp);
       ln.g0 = sg * K;
       ln.ng = std::min(p->C.G, (sg + 1) * K) - sg * K;
+      ln.rec_stride = 1;
+      ln.theta = (const double*)p->theta.p;
       ln.tape = tape + (size_t)l * seg_bytes;
       char* la = aux + (size_t)l * aux_lane;
       ln.rotflag = (int*)la;
@@ -959,7 +1077,7 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
       steps = std::max(steps, ln.ng);
     }
     HIPCHK(hipMemcpyAsync(lanes_d, p->lanes_h.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
-    for (int step = 0; step < steps; ++step) HIPCHK(launch_gate_lanes(lanes_d, nl, lc, step, s));
+    for (int step = 0; step < steps; ++step) HIPCHK(launch_gate_lanes(lanes_d, nl, lc, step, true, s));
     // sizes of the batch's gates (one strided copy per lane and field)
     for (int l = 0; l < nl; ++l) {
       const GateLane& ln = p->lanes_h[l];
@@ -972,46 +1090,44 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
     HIPCHK(hipMemcpyAsync(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (err) fail(MPS_EDEVICE, "a lane barrier of the batched recompute timed out");
+    // adjoint lane records of the whole batch (segments in reverse, gates in
+    // reverse), uploaded once; each gate is then one lane-adjoint launch set
+    rec.clear();
+    dd.clear();
     for (int l = nl - 1; l >= 0; --l) {
       const GateLane& ln = p->lanes_h[l];
-      const int g0 = ln.g0, g1 = ln.g0 + ln.ng;
-      for (int g = g1 - 1; g >= g0; --g) {
-        GateRec R = rec_at(ln.tape, L, g - g0);
-        const int* mt = meta.data() + ((size_t)l * K + (g - g0)) * 16;
-        GateDims d;
-        d.n = p->C.bond_h[g];
-        d.r = mt[0];
-        d.a = mt[4];
-        d.m = mt[5];
-        d.b = mt[6];
-        d.nu = dmeta[((size_t)l * K + (g - g0)) * 16];
-        const int n = d.n;
-        zd* Bbn = Bbar + (size_t)n * site;
-        zd* Bbn1 = Bbar + (size_t)(n + 1) * site;
-        double* lb_out = lambar + (size_t)(n + 1) * dc;
-        double* lb_in = lambar + (size_t)n * dc;
-        const int M = 2 * d.a, nb = 2 * d.b;
-        hipLaunchKernelGGL(k_adj_wbar, gemm_grid(d.r, nb), dim3(256), 0, s, R, W, (const zd*)Bbn, (const zd*)Bbn1, d, dc, gw.ldc);
-        hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, s, R, W, (const zd*)Bbn1, (const double*)lb_out, d, dc, gw.ldv);
-        hipLaunchKernelGGL(k_adj_K, gemm_grid(nb, d.r), dim3(256), 0, s, R, W, d, dc, gw.ldv);
-        hipLaunchKernelGGL(k_adj_kscale, dim3(1), dim3(256), 0, s, W, d, dc);
-        hipLaunchKernelGGL(k_adj_phi, dim3((nb * nb + 255) / 256), dim3(256), 0, s, R, W, d, dc, p->opts.broaden, gw.stats);
-        hipLaunchKernelGGL(k_adj_T, gemm_grid(M, nb), dim3(256), 0, s, R, W, d, gw.ldc);
-        hipLaunchKernelGGL(k_adj_Mbar, gemm_grid(M, nb), dim3(256), 0, s, R, W, d, gw.ldv);
-        hipLaunchKernelGGL(k_adj_Cbar, gemm_grid(M, nb), dim3(256), 0, s, R, W, (const zd*)Bbn, d, dc, gw.ldv);
-        hipLaunchKernelGGL(k_adj_lambar, dim3(d.a), dim3(256), 0, s, R, W, d, lb_in, gw.ldc);
-        const int nparts = (d.a * d.b + 255) / 256;
-        hipLaunchKernelGGL(k_adj_theta, dim3(nparts), dim3(256), 0, s, R, W, p->C.tab, g, th, d, gw.ldc);
-        hipLaunchKernelGGL(k_adj_Bl, gemm_grid(M, d.m), dim3(256), 0, s, R, W, Bbn, d, dc);
-        hipLaunchKernelGGL(k_adj_Br, gemm_grid(d.m, nb), dim3(256), 0, s, R, W, Bbn1, d, dc);
-        hipLaunchKernelGGL(k_adj_finish, dim3(1), dim3(256), 0, s, W, lb_out, dc, nparts, gphi, g, p->C.kind_h[g]);
+      for (int g = ln.g0 + ln.ng - 1; g >= ln.g0; --g) {
+        const size_t k = (size_t)l * K + (g - ln.g0);
+        AdjLane a1;
+        a1.R = rec_at(ln.tape, L, g - ln.g0);
+        a1.W = W;
+        a1.d = dims_of(meta.data() + k * 16, dmeta.data() + k * 16, p->C.bond_h[g]);
+        const int n = a1.d.n;
+        a1.Bbn = Bbar + (size_t)n * site;
+        a1.Bbn1 = Bbar + (size_t)(n + 1) * site;
+        a1.lb_out = lambar + (size_t)(n + 1) * dc;
+        a1.lb_in = lambar + (size_t)n * dc;
+        a1.gphi = gphi;
+        a1.theta = th;
+        rec.push_back(a1);
+        dd.push_back(a1.d);
       }
+    }
+    AdjLane* rec_d = (AdjLane*)p->adjl_dev.ensure(rec.size() * sizeof(AdjLane));
+    HIPCHK(hipMemcpyAsync(rec_d, rec.data(), rec.size() * sizeof(AdjLane), hipMemcpyHostToDevice, s));
+    size_t k = 0;
+    for (int l = nl - 1; l >= 0; --l) {
+      const GateLane& ln = p->lanes_h[l];
+      for (int g = ln.g0 + ln.ng - 1; g >= ln.g0; --g, ++k)
+        launch_gate_adjoint(rec_d + k, 1, dd[k], g, p->C.kind_h[g], p->C.tab, dc, gw, p->opts.broaden, s);
       HIPCHK(hipGetLastError());
       if (ctx->progress) {
         HIPCHK(hipStreamSynchronize(s));
         ctx->progress(ctx->progress_user, "backward", p->n_seg - (lo + l), p->n_seg);
       }
     }
+    // the next batch rewrites the host records only after its metadata copy,
+    // which synchronises the stream (and with it this batch's upload)
   }
   if (!A.chain_built) build_chain(p, A);
   double* gd_dev = (double*)p->grad.ensure((size_t)std::max(1, p->n_theta) * sizeof(double));
@@ -1033,3 +1149,292 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   if (gs.degen_grad > 0 && p->opts.strict_degenerate)
     fail(MPS_EDEGEN, std::to_string(gs.degen_grad) + " degenerate singular pairs carry a cotangent");
 }
+
+// ============================================================================
+// Batched form: energy and gradient of nb parameter vectors of one plan.  The
+// lanes advance through the circuit in lockstep, so every gate step is one
+// launch per kernel for all lanes (the Jacobi SVDs of all lanes in one
+// cooperative launch, each lane with its own barrier); the reverse pass
+// recomputes one checkpoint segment for all lanes at a time and runs the gate
+// adjoint of all lanes in one launch set per gate.
+// ============================================================================
+struct BatchLane {
+  mps_state* st = nullptr;   // forward state
+  mps_state* rp = nullptr;   // segment replay state
+  DevBuf ckpt, Bbar, lambar, gphi, grad, work;
+  double E = 0.0, Eim = 0.0, Z = 0.0;
+  ~BatchLane() {
+    delete st;
+    delete rp;
+  }
+};
+
+struct BatchSet {
+  std::vector<BatchLane*> lanes;
+  DevBuf thetas, tape, aux, lanes_dev, adj_dev;
+  ~BatchSet() {
+    for (BatchLane* l : lanes) delete l;
+  }
+};
+
+static BatchSet& batch_of(mps_plan* p) {
+  PlanAdj& A = adj_of(p);
+  if (!A.batch) A.batch = new BatchSet();
+  return *A.batch;
+}
+
+// One group of nl <= lanes_max lanes; thetas_dev holds nl consecutive vectors.
+static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double* energies, double* grads_dev,
+                          GateStats* gsum) {
+  mps_ctx* ctx = p->ctx;
+  hipStream_t s = ctx->stream;
+  BatchSet& B = batch_of(p);
+  const int N = p->N, G = p->C.G, K = p->opts.ckpt_gates, nth = std::max(1, p->n_theta);
+  const int dc = p->state->dcap;
+  ctx->ensure_gate_work(dc, p->trunc, p->opts.max_sweeps);
+  const GateWork gw = ctx->gw;
+  const TapeLayout L = tape_layout(dc, gw.ncap, gw.ldc, gw.ldv);
+  const int n_seg = (G + K - 1) / K;
+  const size_t site = (size_t)dc * 2 * dc;
+  while ((int)B.lanes.size() < nl) {
+    BatchLane* bl = new BatchLane();
+    B.lanes.push_back(bl);
+    bl->st = plan_new_state(ctx, N, p->trunc, nullptr);
+    bl->rp = plan_new_state(ctx, N, p->trunc, nullptr);
+  }
+  const size_t ckpt_stride = ((p->state->B.bytes + p->state->dims.bytes + p->state->lam.bytes + 255) / 256) * 256;
+  const size_t aux_lane = 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats) + 64;
+  char* aux = (char*)B.aux.ensure((size_t)nl * aux_lane + 64);
+  int* lane_err = (int*)(aux + (size_t)nl * aux_lane);
+  HIPCHK(hipMemsetAsync(aux, 0, (size_t)nl * aux_lane + 64, s));
+  char* tape = (char*)B.tape.ensure((size_t)nl * K * L.rec);
+  GateLane* lanes_d = (GateLane*)B.lanes_dev.ensure((size_t)nl * sizeof(GateLane));
+  std::vector<GateLane> lh(nl);
+  std::vector<AdjWork> W(nl);
+  for (int l = 0; l < nl; ++l) {
+    BatchLane* bl = B.lanes[l];
+    bl->ckpt.ensure((size_t)n_seg * ckpt_stride);
+    bl->Bbar.ensure((size_t)N * site * sizeof(zd));
+    bl->lambar.ensure((size_t)(N + 1) * dc * sizeof(double));
+    bl->gphi.ensure((size_t)std::max(1, G) * sizeof(double));
+    adjwork_layout(gw.ncap, dc, &W[l], (char*)bl->work.ensure(adjwork_layout(gw.ncap, dc, nullptr, nullptr)));
+    HIPCHK(hipMemsetAsync(bl->lambar.p, 0, bl->lambar.bytes, s));
+    HIPCHK(hipMemsetAsync(bl->gphi.p, 0, bl->gphi.bytes, s));
+    char* la = aux + (size_t)l * aux_lane;
+    GateLane& ln = lh[l];
+    ln.rotflag = (int*)la;
+    ln.nrm_part = (double*)(la + 128 * sizeof(int));
+    ln.stats = (GateStats*)(la + 128 * sizeof(int) + 256 * sizeof(double));
+    ln.bar = (unsigned*)(la + 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats));
+    ln.err = lane_err;
+    ln.theta = thetas_dev + (size_t)l * nth;
+  }
+  LaneConst lc;
+  lc.gt = p->C.tab;
+  lc.L = L;
+  lc.ldc = gw.ldc;
+  lc.ldv = gw.ldv;
+  lc.ncap = gw.ncap;
+  lc.dmax = gw.dmax;
+  lc.max_sweeps = gw.max_sweeps;
+  lc.nparts = ((2 * dc + ZT_M - 1) / ZT_M) * ((2 * dc + ZT_M - 1) / ZT_M);
+  lc.eps = gw.eps;
+  lc.tol = gw.tol;
+  // ---- forward: all lanes through the circuit, checkpoint every K gates
+  for (int l = 0; l < nl; ++l) {
+    BatchLane* bl = B.lanes[l];
+    init_product(bl->st, (const uint8_t*)p->state->occ.p);
+    GateLane& ln = lh[l];
+    ln.st = view_of(bl->st);
+    ln.g0 = 0;
+    ln.ng = G;
+    ln.rec_stride = 0;
+    ln.tape = tape + (size_t)l * K * L.rec;
+  }
+  HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
+  for (int g = 0; g < G; ++g) {
+    if (g % K == 0)
+      for (int l = 0; l < nl; ++l) {
+        mps_state* st = B.lanes[l]->st;
+        char* base = (char*)B.lanes[l]->ckpt.p + (size_t)(g / K) * ckpt_stride;
+        HIPCHK(hipMemcpyAsync(base, st->B.p, st->B.bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(base + st->B.bytes, st->dims.p, st->dims.bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(base + st->B.bytes + st->dims.bytes, st->lam.p, st->lam.bytes,
+                              hipMemcpyDeviceToDevice, s));
+      }
+    HIPCHK(launch_gate_lanes(lanes_d, nl, lc, g, false, s));
+    if (ctx->progress && (g + 1) % K == 0) {
+      HIPCHK(hipStreamSynchronize(s));
+      ctx->progress(ctx->progress_user, "forward", (g + 1) / K, n_seg);
+    }
+  }
+  // ---- statistics of the forward pass (the recompute adds to zeroed counters)
+  std::vector<GateStats> st(nl);
+  for (int l = 0; l < nl; ++l)
+    HIPCHK(hipMemcpyAsync(&st[l], lh[l].stats, sizeof(GateStats), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int l = 0; l < nl; ++l) HIPCHK(hipMemsetAsync(lh[l].stats, 0, sizeof(GateStats), s));
+  // ---- energies and sweep adjoints, lane by lane
+  std::vector<int> dims(N + 1);
+  for (int l = 0; l < nl; ++l) {
+    BatchLane* bl = B.lanes[l];
+    run_energy(bl->st, p->H);
+    double ev[3];
+    HIPCHK(hipMemcpyAsync(ev, ctx->sb.energy, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(dims.data(), bl->st->dims.p, (N + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bl->E = ev[0];
+    bl->Eim = ev[1];
+    bl->Z = ev[2];
+    energies[l] = ev[0];
+    run_sweep_adjoint(p, dims, bl->st, (zd*)bl->Bbar.p, bl->E, bl->Z);
+  }
+  // ---- reverse pass, one segment of all lanes at a time
+  std::vector<int> meta((size_t)nl * K * 16);
+  std::vector<double> dmeta((size_t)nl * K * 16);
+  std::vector<AdjLane> rec;
+  std::vector<GateDims> mx;
+  for (int sg = n_seg - 1; sg >= 0; --sg) {
+    const int g0 = sg * K, ng = std::min(G, (sg + 1) * K) - g0;
+    for (int l = 0; l < nl; ++l) {
+      BatchLane* bl = B.lanes[l];
+      const char* base = (const char*)bl->ckpt.p + (size_t)sg * ckpt_stride;
+      mps_state* rp = bl->rp;
+      HIPCHK(hipMemcpyAsync(rp->B.p, base, rp->B.bytes, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(rp->dims.p, base + rp->B.bytes, rp->dims.bytes, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(rp->lam.p, base + rp->B.bytes + rp->dims.bytes, rp->lam.bytes,
+                            hipMemcpyDeviceToDevice, s));
+      GateLane& ln = lh[l];
+      ln.st = view_of(rp);
+      ln.g0 = g0;
+      ln.ng = ng;
+      ln.rec_stride = 1;
+    }
+    HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
+    for (int step = 0; step < ng; ++step) HIPCHK(launch_gate_lanes(lanes_d, nl, lc, step, true, s));
+    for (int l = 0; l < nl; ++l) {
+      HIPCHK(hipMemcpy2DAsync(meta.data() + (size_t)l * K * 16, 16 * sizeof(int), lh[l].tape + L.ometa, L.rec,
+                              16 * sizeof(int), ng, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpy2DAsync(dmeta.data() + (size_t)l * K * 16, 16 * sizeof(double), lh[l].tape + L.odmeta, L.rec,
+                              16 * sizeof(double), ng, hipMemcpyDeviceToHost, s));
+    }
+    int err = 0;
+    HIPCHK(hipMemcpyAsync(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (err) fail(MPS_EDEVICE, "a lane barrier of the batched gate chain timed out");
+    rec.clear();
+    mx.clear();
+    for (int g = g0 + ng - 1; g >= g0; --g) {
+      GateDims m{p->C.bond_h[g], 0, 0, 0, 0, 0.0};
+      for (int l = 0; l < nl; ++l) {
+        BatchLane* bl = B.lanes[l];
+        const size_t k = (size_t)l * K + (g - g0);
+        AdjLane a1;
+        a1.R = rec_at(lh[l].tape, L, g - g0);
+        a1.W = W[l];
+        a1.d = dims_of(meta.data() + k * 16, dmeta.data() + k * 16, p->C.bond_h[g]);
+        const int n = a1.d.n;
+        zd* Bbar = (zd*)bl->Bbar.p;
+        double* lambar = (double*)bl->lambar.p;
+        a1.Bbn = Bbar + (size_t)n * site;
+        a1.Bbn1 = Bbar + (size_t)(n + 1) * site;
+        a1.lb_out = lambar + (size_t)(n + 1) * dc;
+        a1.lb_in = lambar + (size_t)n * dc;
+        a1.gphi = (double*)bl->gphi.p;
+        a1.theta = lh[l].theta;
+        rec.push_back(a1);
+        m.a = std::max(m.a, a1.d.a);
+        m.m = std::max(m.m, a1.d.m);
+        m.b = std::max(m.b, a1.d.b);
+        m.r = std::max(m.r, a1.d.r);
+      }
+      mx.push_back(m);
+    }
+    AdjLane* rec_d = (AdjLane*)B.adj_dev.ensure(rec.size() * sizeof(AdjLane));
+    HIPCHK(hipMemcpyAsync(rec_d, rec.data(), rec.size() * sizeof(AdjLane), hipMemcpyHostToDevice, s));
+    size_t k = 0;
+    for (int g = g0 + ng - 1; g >= g0; --g, ++k)
+      launch_gate_adjoint(rec_d + k * nl, nl, mx[k], g, p->C.kind_h[g], p->C.tab, dc, gw, p->opts.broaden, s);
+    HIPCHK(hipGetLastError());
+    if (ctx->progress) {
+      HIPCHK(hipStreamSynchronize(s));
+      ctx->progress(ctx->progress_user, "backward", n_seg - sg, n_seg);
+    }
+  }
+  // ---- chain rule per lane
+  PlanAdj& A = adj_of(p);
+  if (!A.chain_built) build_chain(p, A);
+  for (int l = 0; l < nl; ++l)
+    hipLaunchKernelGGL(k_chain_rule, dim3((p->n_theta + 255) / 256), dim3(256), 0, s,
+                       (const int*)A.chain_start.p, (const int*)A.chain_list.p, p->C.tab,
+                       (const double*)B.lanes[l]->gphi.p, grads_dev + (size_t)l * nth, p->n_theta);
+  HIPCHK(hipGetLastError());
+  for (const GateStats& x : st) {
+    gsum->disc_sum += x.disc_sum;
+    gsum->disc_max = std::max(gsum->disc_max, x.disc_max);
+    gsum->truncated += x.truncated;
+    gsum->max_sweeps = std::max(gsum->max_sweeps, x.max_sweeps);
+    gsum->noconv += x.noconv;
+    gsum->degenerate_cuts += x.degenerate_cuts;
+    gsum->max_bond = std::max(gsum->max_bond, x.max_bond);
+    gsum->gates += x.gates;
+  }
+}
+
+void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_theta, int on_device,
+                              double* energies, double* grads, mps_stats* stats) {
+  mps_ctx* ctx = p->ctx;
+  hipStream_t s = ctx->stream;
+  if (nb < 1) fail(MPS_EINVAL, "n_batch must be >= 1");
+  if (n_theta != p->n_theta) fail(MPS_EINVAL, "n_theta does not match the circuit");
+  BatchSet& B = batch_of(p);
+  const int nth = std::max(1, n_theta);
+  double* th = (double*)B.thetas.ensure((size_t)nb * nth * sizeof(double));
+  if (n_theta > 0) {
+    std::vector<double> host((size_t)nb * n_theta);
+    if (on_device) {
+      HIPCHK(hipMemcpyAsync(host.data(), thetas, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    } else {
+      std::memcpy(host.data(), thetas, host.size() * sizeof(double));
+    }
+    validate_theta(host.data(), (int)host.size());
+    HIPCHK(hipMemcpy2DAsync(th, nth * sizeof(double), host.data(), n_theta * sizeof(double),
+                            n_theta * sizeof(double), nb, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // host is released at the end of this block
+  }
+  double* gdev = (double*)p->grad.ensure((size_t)nb * nth * sizeof(double));
+  const int per = lanes_max(p->state->dcap);
+  GateStats gsum{};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int b0 = 0; b0 < nb; b0 += per) {
+    const int nl = std::min(per, nb - b0);
+    batched_group(p, nl, th + (size_t)b0 * nth, energies + b0, gdev + (size_t)b0 * nth, &gsum);
+  }
+  HIPCHK(hipEventRecord(e1, s));
+  if (n_theta > 0)
+    HIPCHK(hipMemcpy2DAsync(grads, n_theta * sizeof(double), gdev, nth * sizeof(double), n_theta * sizeof(double),
+                            nb, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (gsum.noconv) fail(MPS_ENOCONV, "Jacobi SVD did not converge in " + std::to_string(p->opts.max_sweeps) + " sweeps");
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->discarded_weight_sum = gsum.disc_sum;
+    stats->discarded_weight_max = gsum.disc_max;
+    stats->max_bond = gsum.max_bond;
+    stats->gates_truncated = gsum.truncated;
+    stats->max_sweeps_used = gsum.max_sweeps;
+    stats->degenerate_cuts = gsum.degenerate_cuts;
+    stats->n_gates_applied = gsum.gates;
+    stats->t_backward_ms = ms;
+  }
+}
+
+PlanAdj::~PlanAdj() { delete batch; }

@@ -109,11 +109,14 @@ struct TapeLayout {
 };
 TapeLayout tape_layout(int dc, int ncap, int ldc, int ldv);
 
-// One lane of a batched segment recompute: gates [g0, g0 + ng) replayed on the
-// lane's own state, one tape record per gate.
+// One lane of a batched gate chain: gates [g0, g0 + ng) applied to the lane's
+// own state with the lane's parameters: a segment recompute (one tape record
+// per gate) or a whole forward pass (one reused record).
 struct GateLane {
   MpsView st;
   int g0, ng;
+  int rec_stride;     // tape records per step (0: every step reuses record 0)
+  const double* theta;
   char* tape;
   GateStats* stats;
   int* rotflag;       // [128] Jacobi sweep counters
@@ -125,7 +128,6 @@ struct GateLane {
 // Launch constants shared by all lanes.
 struct LaneConst {
   GateTable gt;
-  const double* theta;
   TapeLayout L;
   int ldc, ldv, ncap, dmax, max_sweeps, nparts;
   double eps, tol;
@@ -134,7 +136,8 @@ struct LaneConst {
 // Records every gate of up to nl lanes in lockstep: for step = 0 .. max ng - 1
 // the lanes' contractions, one cooperative launch of all lanes' Jacobi SVDs
 // (each lane synchronised by its own barrier) and the site updates.
-hipError_t launch_gate_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, int step, hipStream_t stream);
+hipError_t launch_gate_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, int step, bool record_inputs,
+                             hipStream_t stream);
 int lanes_max(int dcap);
 
 // GATE_TAPE: Jacobi on C~ with the right rotations accumulated in V (the full

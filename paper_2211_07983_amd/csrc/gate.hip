@@ -578,7 +578,7 @@ struct LaneRec {
 };
 
 __device__ inline LaneRec lane_rec(const GateLane& ln, const TapeLayout& L, int step) {
-  char* r = ln.tape + (size_t)step * L.rec;
+  char* r = ln.tape + (size_t)step * ln.rec_stride * L.rec;
   LaneRec R;
   R.Bl = (zd*)(r + L.oBl);
   R.Br = (zd*)(r + L.oBr);
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(256) void k_contract_lanes(const GateLane* lanes, L
   // the lane's barrier counter starts from zero in the SVD launch that follows
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ln.bar = 0u;
   const LaneRec R = lane_rec(ln, c.L, step);
-  contract_body(ln.st, c.gt, ln.g0 + step, c.theta, R.C, R.A, c.ldc, ln.nrm_part, 0, ln.rotflag);
+  contract_body(ln.st, c.gt, ln.g0 + step, ln.theta, R.C, R.A, c.ldc, ln.nrm_part, 0, ln.rotflag);
 }
 
 template <int W>
@@ -717,10 +717,12 @@ int lanes_max(int dcap) {
   return std::max(1, per_cu * cus / P);
 }
 
-hipError_t launch_gate_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, int step, hipStream_t stream) {
+hipError_t launch_gate_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, int step, bool record_inputs,
+                             hipStream_t stream) {
   const int dc = c.ldc / 2;
   const int tiles = (c.ldc + ZT_M - 1) / ZT_M;
-  hipLaunchKernelGGL(k_tape_inputs_lanes, dim3(64, nl), dim3(256), 0, stream, d_lanes, c, step);
+  if (record_inputs)
+    hipLaunchKernelGGL(k_tape_inputs_lanes, dim3(64, nl), dim3(256), 0, stream, d_lanes, c, step);
   hipLaunchKernelGGL(k_contract_lanes, dim3(tiles, tiles, nl), dim3(256), 0, stream, d_lanes, c, step);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

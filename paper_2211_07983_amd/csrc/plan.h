@@ -101,6 +101,7 @@ struct mps_plan {
   std::vector<GateLane> lanes_h;   // host copy of the lane table
   DevBuf lanes_dev;                // device lane table
   DevBuf lane_aux;                 // per-lane counters, partial sums, stats, barrier words
+  DevBuf adjl_dev;                 // adjoint lane records of the current batch
   DevCircuit C;
   DevHamiltonian H;
   DevBuf theta, grad, gphi;

@@ -186,6 +186,21 @@ mps_status mps_energy_grad(mps_plan* plan, const double* theta, int32_t n_theta,
   });
 }
 
+mps_status mps_energy_grad_batched(mps_plan* plan, int32_t n_batch, const double* thetas, int32_t n_theta,
+                                   int32_t theta_on_device, double* energies, double* grads, mps_stats* stats) {
+  if (!plan || !energies || !grads || (n_theta > 0 && !thetas)) return MPS_EINVAL;
+  return guarded(plan->ctx, [&] {
+    plan_energy_grad_batched(plan, n_batch, thetas, n_theta, theta_on_device, energies, grads, stats);
+  });
+}
+
+int32_t mps_plan_batch_width(mps_plan* plan) {
+  if (!plan) return MPS_EINVAL;
+  int32_t w = 0;
+  const mps_status st = guarded(plan->ctx, [&] { w = lanes_max(plan->state->dcap); });
+  return st == MPS_OK ? w : st;
+}
+
 void mps_plan_free(mps_plan* plan) {
   if (!plan) return;
   (void)hipSetDevice(plan->ctx->device);

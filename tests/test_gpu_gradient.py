@@ -53,6 +53,27 @@ def test_paper_threshold_energy_grad_matches_oracle(ctx):
     plan.free()
 
 
+@pytest.mark.parametrize("name,nb", [("c1", 5), ("c2", 3)])
+def test_batched_equals_single(ctx, name, nb):
+    """mps_energy_grad_batched on nb parameter vectors (the configured one and
+    seeded perturbations of it) against mps_energy_grad on each alone, and the
+    configured vector against the oracle."""
+    p, g = configs.load(name)
+    rng = np.random.default_rng(77)
+    thetas = np.stack([p.theta] + [p.theta + 0.05 * rng.normal(size=p.theta.shape) for _ in range(nb - 1)])
+    plan = make_plan(ctx, p, g, ckpt_gates=128)
+    eb, gb, st = plan.energy_grad_batched(thetas)
+    assert st["n_gates_applied"] == nb * g.n_gates
+    for b in range(nb):
+        e1, g1, _ = plan.energy_grad(thetas[b])
+        assert abs(eb[b] - e1) <= 1e-13 * abs(e1)
+        assert np.abs(gb[b] - g1).max() <= 1e-12 * np.abs(g1).max()
+    gold = golden()[name]
+    assert rel(eb[0], gold["E"]) <= 1e-10
+    assert grad_ok(gb[0], np.array(gold["grad"]))
+    plan.free()
+
+
 def test_checkpoint_interval_invariance(ctx):
     p, g = configs.load("c1")
     a = make_plan(ctx, p, g, ckpt_gates=7).energy_grad(p.theta)[1]
