@@ -162,14 +162,17 @@ __device__ inline zd rot_x(const zd u, const zd v, double c, const zd p) { retur
 __device__ inline zd rot_y(const zd u, const zd v, double c, const zd q) { return zadd(zmul(q, u), zscale(v, c)); }
 
 // Loads the two column blocks (q0, q1) of a (and of v when ACC) into LDS with
-// eight independent loads in flight per thread.
+// LB independent loads in flight per thread (the blocks come from other
+// work-groups through the device-coherent level after each round's barrier,
+// so the loads are latency-bound; more in flight means fewer round trips).
+constexpr int LB = 16;
 __device__ inline void load_blocks(zd* dst, int ldst, const zd* src, int lds, int rows, int ncol, int W, int q0,
                                    int q1, bool identity) {
   const int tot = 2 * W * rows;
-  for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * 256) {
-    zd buf[8];
+  for (int e0 = threadIdx.x; e0 < tot; e0 += LB * 256) {
+    zd buf[LB];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < LB; ++u) {
       const int e = e0 + u * 256;
       if (e < tot) {
         const int c = e / rows, r = e - c * rows;
@@ -178,7 +181,7 @@ __device__ inline void load_blocks(zd* dst, int ldst, const zd* src, int lds, in
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < LB; ++u) {
       const int e = e0 + u * 256;
       if (e < tot) {
         const int c = e / rows, r = e - c * rows;

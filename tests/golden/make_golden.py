@@ -20,6 +20,7 @@ from oracle import mps, sector  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_values.json")
 C3_PREFIX = 3000
+C3_GRAD_PREFIX = 2500
 
 
 def exact_config(name):
@@ -44,6 +45,20 @@ def c2_paper():
     return dict(eps=p.eps, E=E, grad=grad.tolist(), bonds=finfo["bonds"])
 
 
+def c3_prefix_grad():
+    """Energy and gradient of the first C3_GRAD_PREFIX gates of C3 at the parity
+    threshold: every middle SVD is full size (256 x 256) and truncates to 128."""
+    import dataclasses
+    p, g = configs.load("c3")
+    pre = dataclasses.replace(g, bond=g.bond[:C3_GRAD_PREFIX], kind=g.kind[:C3_GRAD_PREFIX],
+                              pre=g.pre[:C3_GRAD_PREFIX], post=g.post[:C3_GRAD_PREFIX],
+                              param=g.param[:C3_GRAD_PREFIX], coeff=g.coeff[:C3_GRAD_PREFIX])
+    n_theta = int(pre.param.max()) + 1
+    E, grad, info = mps.energy_grad(p, pre, p.theta, ckpt=256)
+    return dict(gates=C3_GRAD_PREFIX, n_theta=n_theta, E=E, grad=grad[:n_theta].tolist(),
+                degenerate_cuts=int(info.get("degenerate_cuts", 0)) if isinstance(info, dict) else 0)
+
+
 def c3_prefix():
     """The first C3_PREFIX gates of C3 (the middle bonds reach D=128)."""
     p, g = configs.load("c3")
@@ -53,7 +68,7 @@ def c3_prefix():
 
 
 ENTRIES = {"c1": lambda: exact_config("c1"), "c2": lambda: exact_config("c2"), "c2_paper": c2_paper,
-           "c3_prefix": c3_prefix}
+           "c3_prefix": c3_prefix, "c3_prefix_grad": c3_prefix_grad}
 
 
 def main(names):

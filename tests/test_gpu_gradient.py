@@ -74,6 +74,36 @@ def test_batched_equals_single(ctx, name, nb):
     plan.free()
 
 
+def test_sweep_limit_is_reported_as_nonconvergence(ctx):
+    """With one Jacobi sweep allowed the SVDs cannot converge: MPS_ENOCONV and
+    no outputs."""
+    from paper_2211_07983_amd import MPSError
+    from paper_2211_07983_amd._abi import MPS_ENOCONV
+    p, g = configs.load("c1")
+    plan = make_plan(ctx, p, g, max_sweeps=1)
+    with pytest.raises(MPSError) as ei:
+        plan.energy_grad(p.theta)
+    assert ei.value.code == MPS_ENOCONV
+    with pytest.raises(MPSError) as ei:
+        plan.energy_grad_batched(np.stack([p.theta, p.theta]))
+    assert ei.value.code == MPS_ENOCONV
+    plan.free()
+
+
+def test_batched_validation_errors(ctx):
+    from paper_2211_07983_amd import MPSError
+    from paper_2211_07983_amd._abi import MPS_EINVAL
+    p, g = configs.load("c1")
+    plan = make_plan(ctx, p, g)
+    bad = np.stack([p.theta, p.theta])
+    bad[1, 3] = np.nan
+    for th in (bad, np.zeros((2, p.n_theta + 1)), np.zeros((0, p.n_theta))):
+        with pytest.raises(MPSError) as ei:
+            plan.energy_grad_batched(th)
+        assert ei.value.code == MPS_EINVAL
+    plan.free()
+
+
 def test_checkpoint_interval_invariance(ctx):
     p, g = configs.load("c1")
     a = make_plan(ctx, p, g, ckpt_gates=7).energy_grad(p.theta)[1]
