@@ -938,6 +938,41 @@ static void build_chain(mps_plan* p, PlanAdj& A) {
   A.chain_built = true;
 }
 
+// Gate sizes of a batch of lanes, gathered from the tape records into
+// [lane][step][16] ints (r, -, -, -, a, m, b) and doubles (nu) for one copy.
+__global__ void k_gather_meta(const GateLane* lanes, TapeLayout L, int K, int* meta, double* dmeta) {
+  const GateLane& ln = lanes[blockIdx.y];
+  const int step = blockIdx.x, t = threadIdx.x;
+  if (step >= ln.ng || t >= 16) return;
+  const char* r = ln.tape + (size_t)step * L.rec;
+  const size_t o = ((size_t)blockIdx.y * K + step) * 16 + t;
+  meta[o] = ((const int*)(r + L.ometa))[t];
+  dmeta[o] = ((const double*)(r + L.odmeta))[t];
+}
+
+// Copies the gate sizes of nl lanes (K steps each) to the host and checks
+// them: 1 <= r, a, m, b <= dc for every recorded gate.
+static void read_lane_meta(const GateLane* lanes_d, const std::vector<GateLane>& lh, int nl, const TapeLayout& L,
+                           int K, int dc, DevBuf& dbuf, std::vector<int>& meta, std::vector<double>& dmeta,
+                           hipStream_t s) {
+  const size_t cnt = (size_t)nl * K * 16;
+  char* d = (char*)dbuf.ensure(cnt * (sizeof(int) + sizeof(double)));
+  int* dm = (int*)d;
+  double* dd = (double*)(d + cnt * sizeof(int));
+  hipLaunchKernelGGL(k_gather_meta, dim3(K, nl), dim3(64), 0, s, lanes_d, L, K, dm, dd);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(meta.data(), dm, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(dmeta.data(), dd, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int l = 0; l < nl; ++l)
+    for (int k = 0; k < lh[l].ng; ++k) {
+      const int* mt = meta.data() + ((size_t)l * K + k) * 16;
+      const bool ok = mt[0] >= 1 && mt[0] <= dc && mt[4] >= 1 && mt[4] <= dc && mt[5] >= 1 && mt[5] <= dc &&
+                      mt[6] >= 1 && mt[6] <= dc;
+      if (!ok) fail(MPS_EDEVICE, "gate sizes read back from the tape are out of range");
+    }
+}
+
 // Workspace of one lane of the gate adjoint.
 static size_t adjwork_layout(int ncap, int dc, AdjWork* W, char* w) {
   size_t o = 0;
@@ -1078,14 +1113,8 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
     }
     HIPCHK(hipMemcpyAsync(lanes_d, p->lanes_h.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
     for (int step = 0; step < steps; ++step) HIPCHK(launch_gate_lanes(lanes_d, nl, lc, step, true, s));
-    // sizes of the batch's gates (one strided copy per lane and field)
-    for (int l = 0; l < nl; ++l) {
-      const GateLane& ln = p->lanes_h[l];
-      HIPCHK(hipMemcpy2DAsync(meta.data() + (size_t)l * K * 16, 16 * sizeof(int), ln.tape + L.ometa, L.rec,
-                              16 * sizeof(int), ln.ng, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpy2DAsync(dmeta.data() + (size_t)l * K * 16, 16 * sizeof(double), ln.tape + L.odmeta, L.rec,
-                              16 * sizeof(double), ln.ng, hipMemcpyDeviceToHost, s));
-    }
+    // sizes of the batch's gates
+    read_lane_meta(lanes_d, p->lanes_h, nl, L, K, dc, p->meta_dev, meta, dmeta, s);
     int err = 0;
     HIPCHK(hipMemcpyAsync(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1171,7 +1200,7 @@ struct BatchLane {
 
 struct BatchSet {
   std::vector<BatchLane*> lanes;
-  DevBuf thetas, tape, aux, lanes_dev, adj_dev;
+  DevBuf thetas, tape, aux, lanes_dev, adj_dev, meta_dev;
   ~BatchSet() {
     for (BatchLane* l : lanes) delete l;
   }
@@ -1312,12 +1341,7 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
     }
     HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
     for (int step = 0; step < ng; ++step) HIPCHK(launch_gate_lanes(lanes_d, nl, lc, step, true, s));
-    for (int l = 0; l < nl; ++l) {
-      HIPCHK(hipMemcpy2DAsync(meta.data() + (size_t)l * K * 16, 16 * sizeof(int), lh[l].tape + L.ometa, L.rec,
-                              16 * sizeof(int), ng, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpy2DAsync(dmeta.data() + (size_t)l * K * 16, 16 * sizeof(double), lh[l].tape + L.odmeta, L.rec,
-                              16 * sizeof(double), ng, hipMemcpyDeviceToHost, s));
-    }
+    read_lane_meta(lanes_d, lh, nl, L, K, dc, B.meta_dev, meta, dmeta, s);
     int err = 0;
     HIPCHK(hipMemcpyAsync(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1399,8 +1423,7 @@ void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_t
       std::memcpy(host.data(), thetas, host.size() * sizeof(double));
     }
     validate_theta(host.data(), (int)host.size());
-    HIPCHK(hipMemcpy2DAsync(th, nth * sizeof(double), host.data(), n_theta * sizeof(double),
-                            n_theta * sizeof(double), nb, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(th, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));   // host is released at the end of this block
   }
   double* gdev = (double*)p->grad.ensure((size_t)nb * nth * sizeof(double));
@@ -1415,9 +1438,9 @@ void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_t
     batched_group(p, nl, th + (size_t)b0 * nth, energies + b0, gdev + (size_t)b0 * nth, &gsum);
   }
   HIPCHK(hipEventRecord(e1, s));
-  if (n_theta > 0)
-    HIPCHK(hipMemcpy2DAsync(grads, n_theta * sizeof(double), gdev, nth * sizeof(double), n_theta * sizeof(double),
-                            nb, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  if (n_theta > 0)   // nth == n_theta here: rows are contiguous
+    HIPCHK(hipMemcpyAsync(grads, gdev, (size_t)nb * n_theta * sizeof(double),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));

@@ -102,6 +102,7 @@ struct mps_plan {
   DevBuf lanes_dev;                // device lane table
   DevBuf lane_aux;                 // per-lane counters, partial sums, stats, barrier words
   DevBuf adjl_dev;                 // adjoint lane records of the current batch
+  DevBuf meta_dev;                 // gathered gate sizes of the current batch
   DevCircuit C;
   DevHamiltonian H;
   DevBuf theta, grad, gphi;

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from vqe_inputs import configs
-from gpu_util import golden, rel
+from gpu_util import Prefix, golden, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +71,21 @@ def test_batched_equals_single(ctx, name, nb):
     gold = golden()[name]
     assert rel(eb[0], gold["E"]) <= 1e-10
     assert grad_ok(gb[0], np.array(gold["grad"]))
+    plan.free()
+
+
+def test_c3_prefix_energy_grad_matches_oracle(ctx):
+    """First 2500 gates of the 24-qubit D=128 workload: the middle SVDs are
+    256 x 256 and truncate to 128 at every step; E_D and g_D against the oracle."""
+    p, g = configs.load("c3")
+    gold = golden()["c3_prefix_grad"]
+    pre = Prefix(g, gold["gates"])
+    plan = make_plan(ctx, p, pre, ckpt_gates=256)
+    assert plan.n_theta == gold["n_theta"]
+    e, grad, st = plan.energy_grad(p.theta[:plan.n_theta])
+    assert st["max_bond"] == 128 and st["gates_truncated"] > 100
+    assert rel(e, gold["E"]) <= 1e-10
+    assert grad_ok(grad, np.array(gold["grad"]))
     plan.free()
 
 
