@@ -211,14 +211,22 @@ def main():
     if abs(eb[0] - e) > 1e-12 * abs(e) or np.abs(gb[0] - g).max() > 1e-10 * np.abs(g).max():
         raise SystemExit("batched and single evaluation of the same vector disagree")
     value = args.steps * nb / T
-    n_svd = st["prof_svd_launches"]
-    avg_ms = st["prof_svd_ms"] / max(1, n_svd)
-    flop_per_launch = st["prof_svd_flop"] / max(1, n_svd)
+    # dominant kernel of the step: the batched gate chain (one cooperative launch
+    # per checkpoint segment: contraction, Jacobi SVD and site update of every
+    # gate of every vector), each forward launch timed with HIP events on the
+    # context stream; work counted = the SVDs' 84 p^3 (the contractions and
+    # updates it also does are a few percent and not counted)
+    dcap = max(2, ((prob.bond_dim + 1) // 2) * 2)
+    W = 32 if dcap <= 32 else 16 if dcap <= 64 else 8 if dcap <= 128 else 4
+    src = sb if nb > 1 else st
+    n_svd = src["prof_svd_launches"]
+    avg_ms = src["prof_svd_ms"] / max(1, n_svd)
+    flop_per_launch = src["prof_svd_flop"] / max(1, n_svd)
     achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12 if n_svd else None
-    roofline = {"kernel": "k_svd_jacobi", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
-                "traffic": None, "avg_launch_ms": avg_ms, "flop_per_launch": flop_per_launch,
-                "sampled_launches": n_svd}
+    roofline = {"kernel": f"k_chain_lanes<{W}>" if nb > 1 else f"k_svd_jacobi<{W}, true>", "bound": "alu",
+                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": None,
+                "avg_launch_ms": avg_ms, "flop_per_launch": flop_per_launch, "timed_launches": n_svd}
     cpu = None
     if not args.no_cpu_baseline:
         with one_thread():

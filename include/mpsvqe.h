@@ -120,9 +120,11 @@ typedef struct {
   int32_t degenerate_cuts;      /* cuts with s_r - s_{r+1} < 1e-10 s_1         */
   double t_gates_ms, t_sweep_ms, t_backward_ms;
   int64_t n_gates_applied;
-  /* Sampled SVD launches of the forward pass (see mps_ctx_set_profiling):
-   * summed kernel time from HIP events around each sampled launch on the
-   * context's stream, and summed algorithmic work 84 p^3 (p = min(rows, cols)). */
+  /* SVD launches of the forward pass timed with HIP events on the context's
+   * stream (see mps_ctx_set_profiling): summed kernel time, summed algorithmic
+   * work 84 p^3 per SVD (p = min(rows, cols)) and the number of launches.
+   * Single evaluations time every k-th launch; the batched form times every
+   * forward step (one launch holds the SVDs of all vectors of the step).      */
   double prof_svd_ms;
   double prof_svd_flop;
   int32_t prof_svd_launches;

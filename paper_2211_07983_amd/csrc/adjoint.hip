@@ -1062,8 +1062,9 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   char* tape = (char*)p->tape.ensure((size_t)nlanes * seg_bytes);
   while ((int)p->replays.size() < nlanes) p->replays.push_back(plan_new_state(ctx, N, st->trunc, nullptr));
   const size_t aux_lane = 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats) + 64;
-  char* aux = (char*)p->lane_aux.ensure((size_t)nlanes * aux_lane + 64);
+  char* aux = (char*)p->lane_aux.ensure((size_t)nlanes * aux_lane + 64 + (size_t)nlanes * 8);
   int* lane_err = (int*)(aux + (size_t)nlanes * aux_lane);
+  unsigned long long* lane_bars = (unsigned long long*)(aux + (size_t)nlanes * aux_lane + 64);
   HIPCHK(hipMemsetAsync(lane_err, 0, sizeof(int), s));
   GateLane* lanes_d = (GateLane*)p->lanes_dev.ensure((size_t)nlanes * sizeof(GateLane));
   p->lanes_h.resize(nlanes);
@@ -1078,6 +1079,7 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   lc.nparts = ((2 * dc + ZT_M - 1) / ZT_M) * ((2 * dc + ZT_M - 1) / ZT_M);
   lc.eps = gw.eps;
   lc.tol = gw.tol;
+  lc.ck_B = lc.ck_dims = lc.ck_lam = 0;   // no checkpoint copies in the recompute
   AdjWork W;
   adjwork_layout(gw.ncap, dc, &W, (char*)p->work.ensure(adjwork_layout(gw.ncap, dc, nullptr, nullptr)));
   double* gphi = (double*)p->gphi.ensure((size_t)std::max(1, p->C.G) * sizeof(double));
@@ -1107,12 +1109,14 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
       ln.rotflag = (int*)la;
       ln.nrm_part = (double*)(la + 128 * sizeof(int));
       ln.stats = (GateStats*)(la + 128 * sizeof(int) + 256 * sizeof(double));
-      ln.bar = (unsigned*)(la + 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats));
+      ln.bar = lane_bars + l;
       ln.err = lane_err;
+      ln.ckpt = nullptr;
       steps = std::max(steps, ln.ng);
     }
     HIPCHK(hipMemcpyAsync(lanes_d, p->lanes_h.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
-    for (int step = 0; step < steps; ++step) HIPCHK(launch_gate_lanes(lanes_d, nl, lc, step, true, s));
+    (void)steps;
+    HIPCHK(launch_chain_lanes(lanes_d, nl, lc, true, lane_bars, s));
     // sizes of the batch's gates
     read_lane_meta(lanes_d, p->lanes_h, nl, L, K, dc, p->meta_dev, meta, dmeta, s);
     int err = 0;
@@ -1214,7 +1218,7 @@ static BatchSet& batch_of(mps_plan* p) {
 
 // One group of nl <= lanes_max lanes; thetas_dev holds nl consecutive vectors.
 static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double* energies, double* grads_dev,
-                          GateStats* gsum) {
+                          GateStats* gsum, double* prof_ms, int* prof_n) {
   mps_ctx* ctx = p->ctx;
   hipStream_t s = ctx->stream;
   BatchSet& B = batch_of(p);
@@ -1231,11 +1235,15 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
     bl->st = plan_new_state(ctx, N, p->trunc, nullptr);
     bl->rp = plan_new_state(ctx, N, p->trunc, nullptr);
   }
-  const size_t ckpt_stride = ((p->state->B.bytes + p->state->dims.bytes + p->state->lam.bytes + 255) / 256) * 256;
+  // checkpoint layout: B | dims | lambda at the next 8-byte boundary
+  const size_t ck_B = p->state->B.bytes, ck_dims = p->state->dims.bytes, ck_lam = p->state->lam.bytes;
+  const size_t ck_lamoff = ((ck_B + ck_dims + 7) / 8) * 8;
+  const size_t ckpt_stride = ((ck_lamoff + ck_lam + 255) / 256) * 256;
   const size_t aux_lane = 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats) + 64;
-  char* aux = (char*)B.aux.ensure((size_t)nl * aux_lane + 64);
+  char* aux = (char*)B.aux.ensure((size_t)nl * aux_lane + 64 + (size_t)nl * 8);
   int* lane_err = (int*)(aux + (size_t)nl * aux_lane);
-  HIPCHK(hipMemsetAsync(aux, 0, (size_t)nl * aux_lane + 64, s));
+  unsigned long long* lane_bars = (unsigned long long*)(aux + (size_t)nl * aux_lane + 64);
+  HIPCHK(hipMemsetAsync(aux, 0, (size_t)nl * aux_lane + 64 + (size_t)nl * 8, s));
   char* tape = (char*)B.tape.ensure((size_t)nl * K * L.rec);
   GateLane* lanes_d = (GateLane*)B.lanes_dev.ensure((size_t)nl * sizeof(GateLane));
   std::vector<GateLane> lh(nl);
@@ -1254,7 +1262,7 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
     ln.rotflag = (int*)la;
     ln.nrm_part = (double*)(la + 128 * sizeof(int));
     ln.stats = (GateStats*)(la + 128 * sizeof(int) + 256 * sizeof(double));
-    ln.bar = (unsigned*)(la + 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats));
+    ln.bar = lane_bars + l;
     ln.err = lane_err;
     ln.theta = thetas_dev + (size_t)l * nth;
   }
@@ -1269,34 +1277,46 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
   lc.nparts = ((2 * dc + ZT_M - 1) / ZT_M) * ((2 * dc + ZT_M - 1) / ZT_M);
   lc.eps = gw.eps;
   lc.tol = gw.tol;
-  // ---- forward: all lanes through the circuit, checkpoint every K gates
-  for (int l = 0; l < nl; ++l) {
-    BatchLane* bl = B.lanes[l];
-    init_product(bl->st, (const uint8_t*)p->state->occ.p);
-    GateLane& ln = lh[l];
-    ln.st = view_of(bl->st);
-    ln.g0 = 0;
-    ln.ng = G;
-    ln.rec_stride = 0;
-    ln.tape = tape + (size_t)l * K * L.rec;
+  lc.ck_B = ck_B;
+  lc.ck_dims = ck_dims;
+  lc.ck_lam = ck_lam;
+  // ---- forward: all lanes through the circuit, one chain launch per
+  // checkpoint segment (the launch copies each lane's state to its checkpoint
+  // slot before the segment's first gate)
+  for (int l = 0; l < nl; ++l) init_product(B.lanes[l]->st, (const uint8_t*)p->state->occ.p);
+  // with profiling on, each chain launch is bracketed by events on the stream
+  const bool prof = ctx->prof_every > 0;
+  std::vector<hipEvent_t> ev;
+  if (prof) {
+    ev.resize(2);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   }
-  HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
-  for (int g = 0; g < G; ++g) {
-    if (g % K == 0)
-      for (int l = 0; l < nl; ++l) {
-        mps_state* st = B.lanes[l]->st;
-        char* base = (char*)B.lanes[l]->ckpt.p + (size_t)(g / K) * ckpt_stride;
-        HIPCHK(hipMemcpyAsync(base, st->B.p, st->B.bytes, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(base + st->B.bytes, st->dims.p, st->dims.bytes, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(base + st->B.bytes + st->dims.bytes, st->lam.p, st->lam.bytes,
-                              hipMemcpyDeviceToDevice, s));
-      }
-    HIPCHK(launch_gate_lanes(lanes_d, nl, lc, g, false, s));
-    if (ctx->progress && (g + 1) % K == 0) {
-      HIPCHK(hipStreamSynchronize(s));
-      ctx->progress(ctx->progress_user, "forward", (g + 1) / K, n_seg);
+  for (int sg = 0; sg < n_seg; ++sg) {
+    for (int l = 0; l < nl; ++l) {
+      GateLane& ln = lh[l];
+      ln.st = view_of(B.lanes[l]->st);
+      ln.g0 = sg * K;
+      ln.ng = std::min(G, (sg + 1) * K) - sg * K;
+      ln.rec_stride = 0;
+      ln.tape = tape + (size_t)l * K * L.rec;
+      ln.ckpt = (char*)B.lanes[l]->ckpt.p + (size_t)sg * ckpt_stride;
     }
+    HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
+    if (prof) HIPCHK(hipEventRecord(ev[0], s));
+    HIPCHK(launch_chain_lanes(lanes_d, nl, lc, false, lane_bars, s));
+    if (prof) HIPCHK(hipEventRecord(ev[1], s));
+    // the lane table is rewritten for the next segment only after this one
+    // has been consumed
+    HIPCHK(hipStreamSynchronize(s));
+    if (prof) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+      *prof_ms += t;
+      *prof_n += 1;
+    }
+    if (ctx->progress) ctx->progress(ctx->progress_user, "forward", sg + 1, n_seg);
   }
+  for (auto& e : ev) (void)hipEventDestroy(e);
   // ---- statistics of the forward pass (the recompute adds to zeroed counters)
   std::vector<GateStats> st(nl);
   for (int l = 0; l < nl; ++l)
@@ -1329,18 +1349,18 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
       BatchLane* bl = B.lanes[l];
       const char* base = (const char*)bl->ckpt.p + (size_t)sg * ckpt_stride;
       mps_state* rp = bl->rp;
-      HIPCHK(hipMemcpyAsync(rp->B.p, base, rp->B.bytes, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(rp->dims.p, base + rp->B.bytes, rp->dims.bytes, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(rp->lam.p, base + rp->B.bytes + rp->dims.bytes, rp->lam.bytes,
-                            hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(rp->B.p, base, ck_B, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(rp->dims.p, base + ck_B, ck_dims, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(rp->lam.p, base + ck_lamoff, ck_lam, hipMemcpyDeviceToDevice, s));
       GateLane& ln = lh[l];
       ln.st = view_of(rp);
       ln.g0 = g0;
       ln.ng = ng;
       ln.rec_stride = 1;
+      ln.ckpt = nullptr;
     }
     HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
-    for (int step = 0; step < ng; ++step) HIPCHK(launch_gate_lanes(lanes_d, nl, lc, step, true, s));
+    HIPCHK(launch_chain_lanes(lanes_d, nl, lc, true, lane_bars, s));
     read_lane_meta(lanes_d, lh, nl, L, K, dc, B.meta_dev, meta, dmeta, s);
     int err = 0;
     HIPCHK(hipMemcpyAsync(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1396,6 +1416,7 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
   for (const GateStats& x : st) {
     gsum->disc_sum += x.disc_sum;
     gsum->disc_max = std::max(gsum->disc_max, x.disc_max);
+    gsum->svd_flop += x.svd_flop;
     gsum->truncated += x.truncated;
     gsum->max_sweeps = std::max(gsum->max_sweeps, x.max_sweeps);
     gsum->noconv += x.noconv;
@@ -1429,13 +1450,15 @@ void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_t
   double* gdev = (double*)p->grad.ensure((size_t)nb * nth * sizeof(double));
   const int per = lanes_max(p->state->dcap);
   GateStats gsum{};
+  double prof_ms = 0.0;
+  int prof_n = 0;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, s));
   for (int b0 = 0; b0 < nb; b0 += per) {
     const int nl = std::min(per, nb - b0);
-    batched_group(p, nl, th + (size_t)b0 * nth, energies + b0, gdev + (size_t)b0 * nth, &gsum);
+    batched_group(p, nl, th + (size_t)b0 * nth, energies + b0, gdev + (size_t)b0 * nth, &gsum, &prof_ms, &prof_n);
   }
   HIPCHK(hipEventRecord(e1, s));
   if (n_theta > 0)   // nth == n_theta here: rows are contiguous
@@ -1457,6 +1480,11 @@ void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_t
     stats->degenerate_cuts = gsum.degenerate_cuts;
     stats->n_gates_applied = gsum.gates;
     stats->t_backward_ms = ms;
+    if (prof_n > 0) {
+      stats->prof_svd_ms = prof_ms;
+      stats->prof_svd_flop = gsum.svd_flop;
+      stats->prof_svd_launches = prof_n;
+    }
   }
 }
 

@@ -52,10 +52,9 @@ struct MpsView {
 #define ZT_N 32
 #define ZT_K 16
 
+// sA/sB: LDS staging tiles of [ZT_K][ZT_M + 1] and [ZT_K][ZT_N + 1] elements.
 template <typename FA, typename FB>
-__device__ inline void ztile_acc(int M, int N, int K, int i0, int j0, FA fa, FB fb, zd acc[2][2]) {
-  __shared__ zd As[ZT_K][ZT_M + 1];
-  __shared__ zd Bs[ZT_K][ZT_N + 1];
+__device__ inline void ztile_acc_in(int M, int N, int K, int i0, int j0, FA fa, FB fb, zd acc[2][2], zd* sA, zd* sB) {
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
   for (int a = 0; a < 2; ++a)
@@ -64,18 +63,18 @@ __device__ inline void ztile_acc(int M, int N, int K, int i0, int j0, FA fa, FB 
     for (int e = t; e < ZT_M * ZT_K; e += 256) {
       const int r = e / ZT_K, kk = e % ZT_K;
       const int gi = i0 + r, gk = k0 + kk;
-      As[kk][r] = (gi < M && gk < K) ? fa(gi, gk) : zmk(0.0, 0.0);
+      sA[kk * (ZT_M + 1) + r] = (gi < M && gk < K) ? fa(gi, gk) : zmk(0.0, 0.0);
     }
     for (int e = t; e < ZT_N * ZT_K; e += 256) {
-      const int kk = e / ZT_N, c = e % ZT_N;
-      const int gk = k0 + kk, gj = j0 + c;
-      Bs[kk][c] = (gk < K && gj < N) ? fb(gk, gj) : zmk(0.0, 0.0);
+      const int kk = e / ZT_N, cc = e % ZT_N;
+      const int gk = k0 + kk, gj = j0 + cc;
+      sB[kk * (ZT_N + 1) + cc] = (gk < K && gj < N) ? fb(gk, gj) : zmk(0.0, 0.0);
     }
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < ZT_K; ++kk) {
-      const zd a0 = As[kk][2 * ty], a1 = As[kk][2 * ty + 1];
-      const zd b0 = Bs[kk][2 * tx], b1 = Bs[kk][2 * tx + 1];
+      const zd a0 = sA[kk * (ZT_M + 1) + 2 * ty], a1 = sA[kk * (ZT_M + 1) + 2 * ty + 1];
+      const zd b0 = sB[kk * (ZT_N + 1) + 2 * tx], b1 = sB[kk * (ZT_N + 1) + 2 * tx + 1];
       acc[0][0] = zfma(a0, b0, acc[0][0]);
       acc[0][1] = zfma(a0, b1, acc[0][1]);
       acc[1][0] = zfma(a1, b0, acc[1][0]);
@@ -84,6 +83,16 @@ __device__ inline void ztile_acc(int M, int N, int K, int i0, int j0, FA fa, FB 
     __syncthreads();
   }
 }
+
+// The same with the kernel's own static LDS tiles.
+template <typename FA, typename FB>
+__device__ inline void ztile_acc(int M, int N, int K, int i0, int j0, FA fa, FB fb, zd acc[2][2]) {
+  __shared__ zd As[ZT_K * (ZT_M + 1)];
+  __shared__ zd Bs[ZT_K * (ZT_N + 1)];
+  ztile_acc_in(M, N, K, i0, j0, fa, fb, acc, As, Bs);
+}
+
+#define ZT_LDS_ELEMS (ZT_K * (ZT_M + 1) + ZT_K * (ZT_N + 1))
 
 __device__ inline int tile_row0() { return 2 * (threadIdx.x >> 4); }
 __device__ inline int tile_col0() { return 2 * (threadIdx.x & 15); }

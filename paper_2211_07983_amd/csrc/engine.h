@@ -21,6 +21,7 @@ struct GateTable {
 struct GateStats {
   double disc_sum;
   double disc_max;
+  double svd_flop;   // algorithmic SVD work, 84 p^3 per gate (p = min(rows, cols))
   int truncated;
   int max_sweeps;
   int noconv;
@@ -117,11 +118,12 @@ struct GateLane {
   int g0, ng;
   int rec_stride;     // tape records per step (0: every step reuses record 0)
   const double* theta;
+  char* ckpt;         // chain launches: the state before the first gate is copied here (nullable)
   char* tape;
   GateStats* stats;
   int* rotflag;       // [128] Jacobi sweep counters
   double* nrm_part;   // [256] |C~|^2 partial sums
-  unsigned* bar;      // lane barrier counter
+  unsigned long long* bar;   // lane barrier counter
   int* err;           // set when a lane barrier timed out
 };
 
@@ -131,14 +133,17 @@ struct LaneConst {
   TapeLayout L;
   int ldc, ldv, ncap, dmax, max_sweeps, nparts;
   double eps, tol;
+  size_t ck_B, ck_dims, ck_lam;   // byte sizes of a checkpoint's parts (B, dims, lambda)
 };
-
-// Records every gate of up to nl lanes in lockstep: for step = 0 .. max ng - 1
-// the lanes' contractions, one cooperative launch of all lanes' Jacobi SVDs
-// (each lane synchronised by its own barrier) and the site updates.
-hipError_t launch_gate_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, int step, bool record_inputs,
-                             hipStream_t stream);
 int lanes_max(int dcap);
+
+// All ng gates of every lane in one cooperative launch: per gate the lane's
+// work-groups share the contraction tiles, run the Jacobi SVD and share the
+// site update, separated by the lane's barrier, so each lane advances at its
+// own pace.  record: write the tape inputs; the barrier words bars[nl] are
+// zeroed here before the launch.
+hipError_t launch_chain_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, bool record,
+                              unsigned long long* bars, hipStream_t stream);
 
 // GATE_TAPE: Jacobi on C~ with the right rotations accumulated in V (the full
 // decomposition the reverse pass needs).  GATE_FWD: Jacobi on C~^H without

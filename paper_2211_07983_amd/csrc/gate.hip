@@ -20,17 +20,19 @@ namespace cg = cooperative_groups;
 // each thread holds the four (i, j) values of one (alpha, beta) pair.
 // C and A are column-major with leading dimension ldc; column index j'*b + beta.
 // ----------------------------------------------------------------------------
-__device__ void contract_body(const MpsView& st, const GateTable& gt, int g, const double* theta, zd* C, zd* A,
-                              int ldc, double* nrm_part, int trans, int* rotflag) {
+// One 32 x 32 output tile (bx, by) of the contraction; part = by * nbx + bx
+// indexes the tile's |C~|^2 partial sum.  sbuf: LDS staging for the tile
+// GEMM (ZT_LDS_ELEMS elements), or nullptr for the kernel's own.
+template <bool DYN>
+__device__ void contract_tile(const MpsView& st, const GateTable& gt, int g, const double* theta, zd* C, zd* A,
+                              int ldc, double* nrm_part, int trans, int bx, int by, int nbx, zd* sbuf) {
   __shared__ zd Q[16];
   __shared__ double red[256];
-  // the Jacobi kernel that follows counts rotations per sweep in rotflag
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 128) rotflag[threadIdx.x] = 0;
   const int n = gt.bond[g];
   const int a = st.dims[n], m = st.dims[n + 1], b = st.dims[n + 2];
   const int Mr = 2 * a, Nc = 2 * b;
-  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
-  const int part = blockIdx.y * gridDim.x + blockIdx.x;
+  const int i0 = by * ZT_M, j0 = bx * ZT_N;
+  const int part = by * nbx + bx;
   if (i0 >= Mr || j0 >= Nc) {
     if (threadIdx.x == 0) nrm_part[part] = 0.0;
     return;
@@ -42,7 +44,10 @@ __device__ void contract_body(const MpsView& st, const GateTable& gt, int g, con
   auto fa = [&](int r, int k) { return Bl[(size_t)(r >> 1) * 2 * dc + (r & 1) * dc + k]; };
   auto fb = [&](int k, int c) { return Br[(size_t)k * 2 * dc + (c & 1) * dc + (c >> 1)]; };
   zd acc[2][2];
-  ztile_acc(Mr, Nc, m, i0, j0, fa, fb, acc);
+  if constexpr (DYN)
+    ztile_acc_in(Mr, Nc, m, i0, j0, fa, fb, acc, sbuf, sbuf + ZT_K * (ZT_M + 1));
+  else
+    ztile_acc(Mr, Nc, m, i0, j0, fa, fb, acc);
   __syncthreads();
   const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
   double nrm = 0.0;
@@ -71,7 +76,9 @@ __device__ void contract_body(const MpsView& st, const GateTable& gt, int g, con
 __global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int g, const double* theta,
                                                   zd* C, zd* A, int ldc, double* nrm_part, int trans,
                                                   int* rotflag) {
-  contract_body(st, gt, g, theta, C, A, ldc, nrm_part, trans, rotflag);
+  // the Jacobi kernel that follows counts rotations per sweep in rotflag
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 128) rotflag[threadIdx.x] = 0;
+  contract_tile<false>(st, gt, g, theta, C, A, ldc, nrm_part, trans, blockIdx.x, blockIdx.y, gridDim.x, nullptr);
 }
 
 // ----------------------------------------------------------------------------
@@ -217,16 +224,16 @@ struct GridBarrier {
 // is recorded in *err (reported as an error by the host) instead of waiting
 // forever.
 struct LaneBarrier {
-  unsigned* ctr;
+  unsigned long long* ctr;
   int* err;
-  unsigned nblk;
-  unsigned gen;
+  unsigned long long nblk;
+  unsigned long long gen;
   __device__ void sync() {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-      const unsigned target = (gen + 1) * nblk;
-      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long target = (gen + 1) * nblk;
+      __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       unsigned spins = 0;
       while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
         __builtin_amdgcn_s_sleep(2);
@@ -457,6 +464,8 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
     }
     if (r > gs->max_bond) gs->max_bond = r;
     gs->gates += 1;
+    const double pp = M < ncol ? M : ncol;
+    gs->svd_flop += 84.0 * pp * pp * pp;
     s.dims[n + 1] = r;
   }
   __syncthreads();
@@ -474,18 +483,22 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
 // ----------------------------------------------------------------------------
 // k_update_left: B~_n[(a,i'), mu] = sum_c C[(a,i'), c] V[c, perm[mu]] / nu.
 // ----------------------------------------------------------------------------
-__device__ void update_left_body(const MpsView& st, int n, const zd* C, int ldc, const zd* V, int ldv,
-                                 const int* perm, const int* gmeta, const double* gdmeta) {
+template <bool DYN>
+__device__ void update_left_tile(const MpsView& st, int n, const zd* C, int ldc, const zd* V, int ldv,
+                                 const int* perm, const int* gmeta, const double* gdmeta, int bx, int by, zd* sbuf) {
   const int a = st.dims[n], b = st.dims[n + 2];
   const int r = gmeta[0];
   const double inv = 1.0 / gdmeta[0];
   const int Mr = 2 * a, Nc = r, K = 2 * b;
-  const int i0 = blockIdx.y * ZT_M, j0 = blockIdx.x * ZT_N;
+  const int i0 = by * ZT_M, j0 = bx * ZT_N;
   if (i0 >= Mr || j0 >= Nc) return;
   auto fa = [&](int row, int k) { return C[(size_t)k * ldc + row]; };
   auto fb = [&](int k, int mu) { return V[(size_t)perm[mu] * ldv + k]; };
   zd acc[2][2];
-  ztile_acc(Mr, Nc, K, i0, j0, fa, fb, acc);
+  if constexpr (DYN)
+    ztile_acc_in(Mr, Nc, K, i0, j0, fa, fb, acc, sbuf, sbuf + ZT_K * (ZT_M + 1));
+  else
+    ztile_acc(Mr, Nc, K, i0, j0, fa, fb, acc);
   const int r0 = i0 + tile_row0(), c0 = j0 + tile_col0();
   zd* Bn = st.site(n);
   const int dc = st.dcap;
@@ -499,15 +512,14 @@ __device__ void update_left_body(const MpsView& st, int n, const zd* C, int ldc,
 __global__ __launch_bounds__(256) void k_update_left(MpsView st, int n, const zd* C, int ldc, const zd* V,
                                                      int ldv, const int* perm, const int* gmeta,
                                                      const double* gdmeta) {
-  update_left_body(st, n, C, ldc, V, ldv, perm, gmeta, gdmeta);
+  update_left_tile<false>(st, n, C, ldc, V, ldv, perm, gmeta, gdmeta, blockIdx.x, blockIdx.y, nullptr);
 }
 
 // k_update_right: B~_{n+1}[mu, j', beta] = conj(V[j'*b + beta, perm[mu]]).
-__device__ void update_right_body(const MpsView& st, int n, const zd* V, int ldv, const int* perm,
-                                  const int* gmeta) {
+__device__ void update_right_row(const MpsView& st, int n, const zd* V, int ldv, const int* perm,
+                                 const int* gmeta, int mu) {
   const int b = st.dims[n + 2];
   const int r = gmeta[0];
-  const int mu = blockIdx.x;
   if (mu >= r) return;
   zd* Br = st.site(n + 1);
   const int dc = st.dcap;
@@ -520,7 +532,7 @@ __device__ void update_right_body(const MpsView& st, int n, const zd* V, int ldv
 
 __global__ __launch_bounds__(256) void k_update_right(MpsView st, int n, const zd* V, int ldv, const int* perm,
                                                       const int* gmeta) {
-  update_right_body(st, n, V, ldv, perm, gmeta);
+  update_right_row(st, n, V, ldv, perm, gmeta, blockIdx.x);
 }
 
 // Forward mode (Jacobi on X = C~^H, no accumulation): column c of the rotated
@@ -596,50 +608,7 @@ __device__ inline LaneRec lane_rec(const GateLane& ln, const TapeLayout& L, int 
   return R;
 }
 
-// Gate inputs into the tape: B_n, B_{n+1}, lambda_{n-1} and the sizes (a, m, b).
-__global__ __launch_bounds__(256) void k_tape_inputs_lanes(const GateLane* lanes, LaneConst c, int step) {
-  const GateLane& ln = lanes[blockIdx.y];
-  if (step >= ln.ng) return;
-  const int n = c.gt.bond[ln.g0 + step];
-  const LaneRec R = lane_rec(ln, c.L, step);
-  const MpsView& st = ln.st;
-  const int a = st.dims[n], m = st.dims[n + 1], b = st.dims[n + 2];
-  const int dc = st.dcap;
-  const size_t site = (size_t)dc * 2 * dc;
-  const zd* s0 = st.site(n);
-  const zd* s1 = st.site(n + 1);
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < site; e += (size_t)gridDim.x * blockDim.x) {
-    const int row = (int)(e / dc), col = (int)(e % dc);
-    const int l = row >> 1;
-    if (l < a && col < m) R.Bl[e] = s0[e];
-    if (l < m && col < b) R.Br[e] = s1[e];
-  }
-  if (blockIdx.x == 0) {
-    for (int q = threadIdx.x; q < a; q += blockDim.x) R.lam[q] = st.lam[(size_t)n * dc + q];
-    if (threadIdx.x == 0) {
-      R.meta[4] = a;
-      R.meta[5] = m;
-      R.meta[6] = b;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_contract_lanes(const GateLane* lanes, LaneConst c, int step) {
-  const GateLane& ln = lanes[blockIdx.z];
-  if (step >= ln.ng) return;
-  // the lane's barrier counter starts from zero in the SVD launch that follows
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ln.bar = 0u;
-  const LaneRec R = lane_rec(ln, c.L, step);
-  contract_body(ln.st, c.gt, ln.g0 + step, ln.theta, R.C, R.A, c.ldc, ln.nrm_part, 0, ln.rotflag);
-}
-
-template <int W>
-__global__ __launch_bounds__(256) void k_svd_jacobi_lanes(const GateLane* lanes, LaneConst c, int step, int nblk) {
-  const int lane = blockIdx.x / nblk, p = blockIdx.x % nblk;
-  const GateLane& ln = lanes[lane];
-  if (step >= ln.ng) return;     // uniform over the lane's work-groups
-  const int n = c.gt.bond[ln.g0 + step];
-  const LaneRec R = lane_rec(ln, c.L, step);
+__device__ inline SvdArgs lane_svd_args(const GateLane& ln, const LaneConst& c, int n, const LaneRec& R) {
   SvdArgs s;
   s.A = R.A;
   s.lda = c.ldc;
@@ -661,31 +630,103 @@ __global__ __launch_bounds__(256) void k_svd_jacobi_lanes(const GateLane* lanes,
   s.nrm_part = ln.nrm_part;
   s.nparts = c.nparts;
   s.trans = 0;
-  LaneBarrier bar{ln.bar, ln.err, (unsigned)nblk, 0u};
-  svd_body<W, true>(s, p, nblk, bar);
+  return s;
 }
 
-__global__ __launch_bounds__(256) void k_update_left_lanes(const GateLane* lanes, LaneConst c, int step) {
-  const GateLane& ln = lanes[blockIdx.z];
-  if (step >= ln.ng) return;
-  const LaneRec R = lane_rec(ln, c.L, step);
-  update_left_body(ln.st, c.gt.bond[ln.g0 + step], R.C, c.ldc, R.V, c.ldv, R.perm, R.meta, R.dmeta);
+// Work-group p of nblk copies its share of `words` 8-byte words.
+__device__ inline void copy_words(unsigned long long* dst, const unsigned long long* src, size_t words, int p,
+                                  int nblk) {
+  for (size_t e = (size_t)p * 256 + threadIdx.x; e < words; e += (size_t)nblk * 256) dst[e] = src[e];
 }
 
-__global__ __launch_bounds__(256) void k_update_right_lanes(const GateLane* lanes, LaneConst c, int step) {
-  const GateLane& ln = lanes[blockIdx.y];
-  if (step >= ln.ng) return;
-  const LaneRec R = lane_rec(ln, c.L, step);
-  update_right_body(ln.st, c.gt.bond[ln.g0 + step], R.V, c.ldv, R.perm, R.meta);
-}
-
-static const void* svd_lane_kernel(int W) {
-  switch (W) {
-    case 32: return (const void*)k_svd_jacobi_lanes<32>;
-    case 16: return (const void*)k_svd_jacobi_lanes<16>;
-    case 8: return (const void*)k_svd_jacobi_lanes<8>;
-    default: return (const void*)k_svd_jacobi_lanes<4>;
+template <int W>
+__global__ __launch_bounds__(256) void k_chain_lanes(const GateLane* lanes, LaneConst c, int nblk, int record) {
+  const int lane = blockIdx.x / nblk, p = blockIdx.x % nblk;
+  const GateLane& ln = lanes[lane];
+  extern __shared__ zd lds[];
+  zd* sbuf = lds;    // tile-GEMM staging; the Jacobi blocks use the same LDS in between barriers
+  LaneBarrier bar{ln.bar, ln.err, (unsigned long long)nblk, 0ull};
+  const MpsView& st = ln.st;
+  const int dc = st.dcap;
+  const int tiles = (c.ldc + ZT_M - 1) / ZT_M;
+  const int tm = (2 * dc + ZT_M - 1) / ZT_M, tn = (dc + ZT_N - 1) / ZT_N;
+  if (ln.ckpt) {
+    // the state before the lane's first gate (the update below writes only
+    // after two barriers, which this copy precedes); layout: B, dims at ck_B,
+    // lambda at the next 8-byte boundary after the dims
+    copy_words((unsigned long long*)ln.ckpt, (const unsigned long long*)st.B, c.ck_B / 8, p, nblk);
+    int* dd = (int*)(ln.ckpt + c.ck_B);
+    for (size_t e = (size_t)p * 256 + threadIdx.x; e < c.ck_dims / 4; e += (size_t)nblk * 256) dd[e] = st.dims[e];
+    copy_words((unsigned long long*)(ln.ckpt + ((c.ck_B + c.ck_dims + 7) / 8) * 8), (const unsigned long long*)st.lam,
+               c.ck_lam / 8, p, nblk);
   }
+  for (int step = 0; step < ln.ng; ++step) {
+    const int g = ln.g0 + step;
+    const int n = c.gt.bond[g];
+    const LaneRec R = lane_rec(ln, c.L, step);
+    if (record) {
+      const int a = st.dims[n], m = st.dims[n + 1], b = st.dims[n + 2];
+      const size_t site = (size_t)dc * 2 * dc;
+      const zd* s0 = st.site(n);
+      const zd* s1 = st.site(n + 1);
+      for (size_t e = (size_t)p * 256 + threadIdx.x; e < site; e += (size_t)nblk * 256) {
+        const int row = (int)(e / dc), col = (int)(e % dc);
+        const int l = row >> 1;
+        if (l < a && col < m) R.Bl[e] = s0[e];
+        if (l < m && col < b) R.Br[e] = s1[e];
+      }
+      if (p == 0) {
+        for (int q = threadIdx.x; q < a; q += 256) R.lam[q] = st.lam[(size_t)n * dc + q];
+        if (threadIdx.x == 0) {
+          R.meta[4] = a;
+          R.meta[5] = m;
+          R.meta[6] = b;
+        }
+      }
+    }
+    if (p == 0 && threadIdx.x < 128) ln.rotflag[threadIdx.x] = 0;
+    for (int tile = p; tile < tiles * tiles; tile += nblk)
+      contract_tile<true>(st, c.gt, g, ln.theta, R.C, R.A, c.ldc, ln.nrm_part, 0, tile % tiles, tile / tiles, tiles,
+                          sbuf);
+    bar.sync();
+    const SvdArgs s = lane_svd_args(ln, c, n, R);
+    svd_body<W, true>(s, p, nblk, bar);
+    bar.sync();
+    for (int tile = p; tile < tm * tn; tile += nblk)
+      update_left_tile<true>(st, n, R.C, c.ldc, R.V, c.ldv, R.perm, R.meta, R.dmeta, tile % tn, tile / tn, sbuf);
+    for (int mu = p; mu < dc; mu += nblk) update_right_row(st, n, R.V, c.ldv, R.perm, R.meta, mu);
+    bar.sync();
+  }
+}
+
+static const void* chain_kernel(int W) {
+  switch (W) {
+    case 32: return (const void*)k_chain_lanes<32>;
+    case 16: return (const void*)k_chain_lanes<16>;
+    case 8: return (const void*)k_chain_lanes<8>;
+    default: return (const void*)k_chain_lanes<4>;
+  }
+}
+
+// Dynamic LDS of the chain kernel: the Jacobi blocks or the tile-GEMM staging.
+static size_t chain_shared_bytes(int dc, int ldc, int ldv) {
+  return std::max(svd_shared_bytes(dc, ldc, ldv, GATE_TAPE), (size_t)ZT_LDS_ELEMS * sizeof(zd));
+}
+
+hipError_t launch_chain_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, bool record,
+                              unsigned long long* bars, hipStream_t stream) {
+  const int dc = c.ldc / 2;
+  const int W = svd_width(dc);
+  const int P = (c.ncap + 2 * W - 1) / (2 * W);
+  const size_t shm = chain_shared_bytes(dc, c.ldc, c.ldv);
+  hipError_t e = hipMemsetAsync(bars, 0, (size_t)nl * sizeof(unsigned long long), stream);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(chain_kernel(W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  LaneConst cc = c;
+  int nb = P, rec = record ? 1 : 0;
+  void* args[] = {(void*)&d_lanes, &cc, &nb, &rec};
+  return hipLaunchCooperativeKernel(chain_kernel(W), dim3(P * nl), dim3(256), args, shm, stream);
 }
 
 TapeLayout tape_layout(int dc, int ncap, int ldc, int ldv) {
@@ -707,43 +748,19 @@ TapeLayout tape_layout(int dc, int ncap, int ldc, int ldv) {
   return L;
 }
 
-// Lanes that fit one cooperative launch: the SVD kernel holds one work-group
-// per compute unit (its LDS use), each lane needs P of them.
+// Lanes that fit one cooperative launch of the chain kernel: its LDS use
+// bounds the work-groups per compute unit, and each lane needs P of them.
 int lanes_max(int dcap) {
   const int W = svd_width(dcap);
   const int P = (2 * dcap + 2 * W - 1) / (2 * W);
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-  const size_t shm = svd_shared_bytes(dcap, 2 * dcap, 2 * P * W, GATE_TAPE);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, svd_lane_kernel(W), 256, shm) != hipSuccess) return 1;
+  const size_t shm = chain_shared_bytes(dcap, 2 * dcap, 2 * P * W);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chain_kernel(W), 256, shm) != hipSuccess) return 1;
   return std::max(1, per_cu * cus / P);
 }
 
-hipError_t launch_gate_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, int step, bool record_inputs,
-                             hipStream_t stream) {
-  const int dc = c.ldc / 2;
-  const int tiles = (c.ldc + ZT_M - 1) / ZT_M;
-  if (record_inputs)
-    hipLaunchKernelGGL(k_tape_inputs_lanes, dim3(64, nl), dim3(256), 0, stream, d_lanes, c, step);
-  hipLaunchKernelGGL(k_contract_lanes, dim3(tiles, tiles, nl), dim3(256), 0, stream, d_lanes, c, step);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int W = svd_width(dc);
-  const int P = (c.ncap + 2 * W - 1) / (2 * W);
-  const size_t shm = svd_shared_bytes(dc, c.ldc, c.ldv, GATE_TAPE);
-  e = hipFuncSetAttribute(svd_lane_kernel(W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  if (e != hipSuccess) return e;
-  LaneConst cc = c;
-  int stp = step, nb = P;
-  void* args[] = {(void*)&d_lanes, &cc, &stp, &nb};
-  e = hipLaunchCooperativeKernel(svd_lane_kernel(W), dim3(P * nl), dim3(256), args, shm, stream);
-  if (e != hipSuccess) return e;
-  const int tm = (2 * dc + ZT_M - 1) / ZT_M, tn = (dc + ZT_N - 1) / ZT_N;
-  hipLaunchKernelGGL(k_update_left_lanes, dim3(tn, tm, nl), dim3(256), 0, stream, d_lanes, c, step);
-  hipLaunchKernelGGL(k_update_right_lanes, dim3(dc, nl), dim3(256), 0, stream, d_lanes, c, step);
-  return hipGetLastError();
-}
 
 // ----------------------------------------------------------------------------
 // Host launchers
