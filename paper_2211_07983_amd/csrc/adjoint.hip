@@ -1184,12 +1184,12 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
 }
 
 // ============================================================================
-// Batched form: energy and gradient of nb parameter vectors of one plan.  The
-// lanes advance through the circuit in lockstep, so every gate step is one
-// launch per kernel for all lanes (the Jacobi SVDs of all lanes in one
-// cooperative launch, each lane with its own barrier); the reverse pass
-// recomputes one checkpoint segment for all lanes at a time and runs the gate
-// adjoint of all lanes in one launch set per gate.
+// Batched form: energy and gradient of nb parameter vectors of one plan.  Each
+// vector is a lane of the gate-chain kernel: one cooperative launch per
+// checkpoint segment takes every lane through the segment's gates, each lane
+// on its own work-groups and barrier; the reverse pass recomputes one
+// checkpoint segment for all lanes at a time and runs the gate adjoint of all
+// lanes in one launch set per gate.
 // ============================================================================
 struct BatchLane {
   mps_state* st = nullptr;   // forward state

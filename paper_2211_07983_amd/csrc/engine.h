@@ -29,7 +29,7 @@ struct GateStats {
   int max_bond;
   int gates;
   int degen_grad;    // degenerate pairs that carried a cotangent (backward)
-  int pad;
+  int barrier_timeout;  // a work-group barrier of the SVD timed out (results invalid)
 };
 
 // Workspace of one gate update.
@@ -61,6 +61,7 @@ struct SvdArgs {
   int* gmeta;
   double* gdmeta;
   int* rotflag;
+  unsigned long long* bar;  // work-group barrier counter (zeroed before the launch)
   double* lam_out;
   GateStats* stats;
   double eps;

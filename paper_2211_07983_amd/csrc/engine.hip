@@ -61,7 +61,7 @@ void mps_ctx::ensure_gate_work(int dcap, const mps_trunc& tr, int max_sweeps) {
   gw.perm = (int*)b_perm.ensure((size_t)ncap * sizeof(int));
   gw.gmeta = (int*)b_gmeta.ensure(16 * sizeof(int));
   gw.gdmeta = (double*)b_gdmeta.ensure(16 * sizeof(double));
-  gw.rotflag = (int*)b_rot.ensure(128 * sizeof(int));
+  gw.rotflag = (int*)b_rot.ensure(128 * sizeof(int) + 64);   // flags, then the SVD barrier counter
   gw.nrm_part = (double*)b_nrm.ensure(256 * sizeof(double));
   gw.stats = (GateStats*)b_stats.ensure(sizeof(GateStats));
   gw.eps = tr.eps;
@@ -346,6 +346,7 @@ void read_stats(mps_ctx* ctx, mps_stats* out, int64_t gates) {
   GateStats gs;
   HIPCHK(hipMemcpyAsync(&gs, ctx->gw.stats, sizeof(GateStats), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (gs.barrier_timeout) fail(MPS_EDEVICE, "a work-group barrier of the Jacobi SVD timed out");
   if (gs.noconv) fail(MPS_ENOCONV, "Jacobi SVD did not converge in " + std::to_string(ctx->gw.max_sweeps) + " sweeps");
   if (out) {
     out->discarded_weight_sum = gs.disc_sum;

@@ -6,13 +6,11 @@
 //   B~_n = C W_r^dagger / nu, B~_{n+1} = W_r, lambda_n = s_r / nu   (k_update_*)
 // All sizes are read from the device-side bond dimensions, so a whole circuit
 // is enqueued without any host synchronisation.
-#include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
 
 #include "engine.h"
 
-namespace cg = cooperative_groups;
 
 // ----------------------------------------------------------------------------
 // k_contract: C[(a,i'),(j',b)] = sum_{ij} Q[(i'j'),(ij)] sum_g B_n[a,i,g] B_{n+1}[g,j,b]
@@ -77,7 +75,8 @@ __global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int 
                                                   zd* C, zd* A, int ldc, double* nrm_part, int trans,
                                                   int* rotflag) {
   // the Jacobi kernel that follows counts rotations per sweep in rotflag
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 128) rotflag[threadIdx.x] = 0;
+  // and synchronises its work-groups on the counter after the 128 flags
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 130) rotflag[threadIdx.x] = 0;
   contract_tile<false>(st, gt, g, theta, C, A, ldc, nrm_part, trans, blockIdx.x, blockIdx.y, gridDim.x, nullptr);
 }
 
@@ -207,35 +206,30 @@ __device__ inline void store_blocks(zd* dst, int ldd, const zd* src, int lsrc, i
   }
 }
 
-// Barrier over all work-groups of a cooperative launch (one SVD per launch).
-struct GridBarrier {
-  cg::grid_group g;
-  __device__ void sync() {
-    __threadfence();
-    g.sync();
-  }
-};
-
-// Barrier over the nblk work-groups of one lane of a batched cooperative
-// launch: a monotonic counter (zeroed before the launch) that every
-// work-group increments once per barrier; barrier k completes when it reaches
-// (k + 1) nblk.  The launch is cooperative, so every work-group of the lane is
-// resident and the wait ends; the spin is bounded all the same and a timeout
-// is recorded in *err (reported as an error by the host) instead of waiting
-// forever.
+// Barrier over the nblk work-groups of one SVD (the whole grid of a
+// single-SVD launch, or one lane of a batched launch): a monotonic counter,
+// zeroed before the launch, that every work-group increments once per
+// barrier; barrier k completes when it reaches (k + 1) nblk.  The launches
+// are cooperative, so every work-group is resident and the wait ends; the spin
+// is bounded all the same and a timeout is recorded in *err (reported as an
+// error by the host) instead of waiting forever.
 struct LaneBarrier {
   unsigned long long* ctr;
   int* err;
   unsigned long long nblk;
   unsigned long long gen;
   __device__ void sync() {
-    __threadfence();
+    // every wave's stores of the phase written back before the arrival (the
+    // work-group barrier alone does not wait for global stores)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
       const unsigned long long target = (gen + 1) * nblk;
       __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      // relaxed polls: an acquire load would invalidate the caches on every
+      // poll, under every other lane resident on the same L2
       unsigned spins = 0;
-      while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         __builtin_amdgcn_s_sleep(2);
         // about a second: far beyond one Jacobi round; after a timeout every
         // later wait of the launch ends at once
@@ -244,7 +238,9 @@ struct LaneBarrier {
           break;
         }
       }
-      __threadfence();
+      // one acquire after the wait: the other work-groups' stores are visible
+      // to this compute unit
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     ++gen;
     __syncthreads();
@@ -476,7 +472,7 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
 
 template <int W, bool ACC>
 __global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
-  GridBarrier bar{cg::this_grid()};
+  LaneBarrier bar{s.bar, &s.stats->barrier_timeout, (unsigned long long)gridDim.x, 0ull};
   svd_body<W, ACC>(s, blockIdx.x, gridDim.x, bar);
 }
 
@@ -621,6 +617,7 @@ __device__ inline SvdArgs lane_svd_args(const GateLane& ln, const LaneConst& c, 
   s.gmeta = R.meta;
   s.gdmeta = R.dmeta;
   s.rotflag = ln.rotflag;
+  s.bar = ln.bar;
   s.lam_out = ln.st.lam + (size_t)(n + 1) * ln.st.dcap;
   s.stats = ln.stats;
   s.eps = c.eps;
@@ -793,6 +790,7 @@ static SvdArgs svd_args(const MpsView& st, int bond, GateWork& w, GateMode mode)
   s.gmeta = w.gmeta;
   s.gdmeta = w.gdmeta;
   s.rotflag = w.rotflag;
+  s.bar = (unsigned long long*)(w.rotflag + 128);
   s.lam_out = st.lam + (size_t)(bond + 1) * st.dcap;
   s.stats = w.stats;
   s.eps = w.eps;
