@@ -23,9 +23,16 @@ well and reported as `single`.  Inputs are resident on the device before the
 timed region.
 
 Prints one JSON line on stdout; progress lines go to stderr.  The roofline
-object refers to the dominant kernel, the Jacobi SVD, timed with HIP events
-around sampled launches on the stream the kernel runs on; the CPU baseline
-times the FP64 oracle on the same workload on the host cores.
+object refers to the dominant kernel, the persistent gate chain (one
+cooperative launch per checkpoint segment, whose time is almost all Jacobi
+SVD), timed with HIP events around its launches on the stream it runs on; the
+CPU baseline times the FP64 oracle on the same workload on the host cores.
+
+--phase sweep measures the Pauli-sweep phase alone (S5 + S6: identity
+environments, every term's transfers, the compensated energy sum) on the
+state after the first --prefix-gates gates of the workload, in plain FP64 and
+in precision mode 1 (transfers as complex FP32 products on the matrix cores),
+and prints its own JSON line with the matrix-core roofline of that phase.
 """
 from __future__ import annotations
 
@@ -39,6 +46,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 (vector and matrix): 256 CU x 2.4 GHz x 128 flop/clk
+PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix: 256 CU x 2.4 GHz x 256 flop/clk
 METRIC = "energy+grad evals/s (UCCSD-MPS 24q D=128) vs plain FP64; MFMA util %"
 WORKLOADS = {
     "c3": "UCCSD-MPS 24 qubits (12 orbitals, 12 electrons), D=128",
@@ -149,6 +157,78 @@ def cpu_baseline_sample(prob, gates, eps, budget_s=25.0):
             "seconds_per_eval": per_eval}
 
 
+def sweep_cmacs(dims, hx, hz):
+    """Complex multiply-adds of one sweep: every (term, site) transfer is two
+    GEMMs, a*a*2b + 2a*b*b = 2ab(a+b) with a, b the bonds left and right of the
+    site; the left and right identity environments add one transfer per site
+    each."""
+    N = len(dims) - 1
+    per_site = [2 * dims[n] * dims[n + 1] * (dims[n] + dims[n + 1]) for n in range(N)]
+    active = [0] * (N + 1)
+    for x, z in zip(hx, hz):
+        m = int(x) | int(z)
+        active[(m & -m).bit_length() - 1] += 1
+        active[m.bit_length()] -= 1
+    total, run = 0, 0
+    for n in range(N):
+        run += active[n]
+        total += run * per_site[n]
+    return total + 2 * sum(per_site)
+
+
+class _GatePrefix:
+    def __init__(self, gl, count):
+        self.n_qubits = gl.n_qubits
+        for f in ("bond", "kind", "pre", "post", "param", "coeff"):
+            setattr(self, f, getattr(gl, f)[:count])
+
+
+def sweep_phase(args):
+    import numpy as np
+    from vqe_inputs import configs
+    from paper_2211_07983_amd import Context, State
+    prob, gates = configs.load(args.workload, eps=args.eps)
+    G = min(args.prefix_gates, gates.n_gates)
+    pre = _GatePrefix(gates, G)
+    ctx = Context(0)
+    res = {}
+    for prec in (0, 1):
+        st = State.product(ctx, prob.occ, prob.bond_dim, prob.eps, precision=prec)
+        t = time.perf_counter()
+        st.apply_circuit(pre, prob.theta)
+        log(f"precision {prec}: {G} gates applied in {time.perf_counter() - t:.1f}s")
+        e, _, _ = st.expect(prob.n_qubits, prob.ham_x, prob.ham_z, prob.ham_c, prob.c0)   # warm-up
+        times = []
+        for _ in range(max(1, args.steps)):
+            e, _, s = st.expect(prob.n_qubits, prob.ham_x, prob.ham_z, prob.ham_c, prob.c0)
+            times.append(s["t_sweep_ms"])
+        dims = [int(d) for d in st.export()[0]]
+        res[prec] = dict(E=e, ms=float(np.median(times)), dims=dims)
+        log(f"precision {prec}: sweep {res[prec]['ms']:.1f} ms (median of {len(times)}), E={e:.12f}")
+        st.free()
+    dims = res[0]["dims"]
+    cmac = sweep_cmacs(dims, prob.ham_x, prob.ham_z)
+    ms32 = res[1]["ms"]
+    eff = 8.0 * cmac / (ms32 * 1e-3) / 1e12
+    line = {
+        "metric": "Pauli-sweep energy evaluations/s (all terms, S5+S6), precision 1 vs plain FP64",
+        "value": 1e3 / ms32, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": ms32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-mfma (FP64 term sums)", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload] + f", eps={prob.eps:g}, K={prob.n_terms} Pauli terms, "
+                               f"state after the first {G} gates", "bonds": dims,
+                   "fp64_ms": res[0]["ms"], "speedup_vs_fp64": res[0]["ms"] / ms32,
+                   "energy_error_ha": abs(res[1]["E"] - res[0]["E"]), "E_fp64": res[0]["E"]},
+        "roofline": {"kernel": "k_left1_f32 + k_left2_f32 (whole sweep phase)", "bound": "mfma",
+                     "achieved": eff, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": eff / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                     "issued_tflops": 0.75 * eff, "cmac_per_sweep": cmac,
+                     "fp64_achieved": 8.0 * cmac / (res[0]["ms"] * 1e-3) / 1e12},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,12 +241,18 @@ def main():
     ap.add_argument("--ckpt-gates", type=int, default=512)
     ap.add_argument("--profile-every", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phase", choices=["evalgrad", "sweep"], default="evalgrad")
+    ap.add_argument("--prefix-gates", type=int, default=3000,
+                    help="--phase sweep: gates applied before the sweeps are timed")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the hot path runs on a single GPU in this build "
               "(the multi-GPU split is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.phase == "sweep":
+        sweep_phase(args)
+        return
     import numpy as np
     from vqe_inputs import configs
     from paper_2211_07983_amd import Context, Plan

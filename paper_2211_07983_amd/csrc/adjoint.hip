@@ -797,6 +797,9 @@ static void run_sweep_adjoint(mps_plan* p, const std::vector<int>& dims, const m
   mps_ctx* ctx = p->ctx;
   hipStream_t s = ctx->stream;
   SweepAdjPlan& S = adj_of(p).sw;
+  // precision 1 computed the energy on FP32 environments: the adjoint takes
+  // the FP64 ones of the same state
+  if (st->trunc.precision == 1) run_identity_envs(const_cast<mps_state*>(st));
   if (!S.built || S.dims != dims || S.lid != ctx->sb.Lid || S.rid != ctx->sb.Rid) build_sweep_adjoint(p, S, dims);
   const int N = p->N, dc = S.dc;
   const size_t dd = (size_t)dc * dc;

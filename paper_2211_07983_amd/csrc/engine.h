@@ -184,6 +184,17 @@ struct SweepBuffers {
   int chunk;
 };
 
+// FP32 copies used by the matrix-core sweep (precision 1); same layouts.
+typedef float2 cf;  // complex float, (x, y) = (re, im)
+struct Sweep32 {
+  cf* B;          // [N][dcap][2][dcap] FP32 copies of the sites
+  cf* Lid;        // [N+1][dcap][dcap]
+  cf* Rid;        // [N+1][dcap][dcap]
+  cf* Lslots;     // [chunk][dcap][dcap]
+  cf* Y;          // [chunk][dcap][2 dcap]
+  cf* Yid;        // [2 dcap][dcap]
+};
+
 hipError_t launch_identity_envs(const MpsView& st, SweepBuffers& sb, hipStream_t stream);
 hipError_t launch_transfer(const MpsView& st, SweepBuffers& sb, int n, const SweepJob* jobs, int njobs,
                            hipStream_t stream);
@@ -191,5 +202,13 @@ hipError_t launch_finalize(const MpsView& st, SweepBuffers& sb, int n, const int
                            int nfin, hipStream_t stream);
 hipError_t launch_energy_sum(const MpsView& st, SweepBuffers& sb, const double* coeff, int64_t K, double c0,
                              hipStream_t stream);
+
+hipError_t launch_sites_f32(const MpsView& st, cf* B32, hipStream_t stream);
+hipError_t launch_identity_envs_f32(const MpsView& st, Sweep32& s, hipStream_t stream);
+hipError_t launch_transfer_f32(const MpsView& st, Sweep32& s, int n, const SweepJob* jobs, int njobs,
+                               hipStream_t stream);
+hipError_t launch_finalize_f32(const MpsView& st, Sweep32& s, zd* termval, int n, const int* slots,
+                               const int* terms, int nfin, hipStream_t stream);
+hipError_t launch_norm_from_f32(const MpsView& st, Sweep32& s, zd* dst, hipStream_t stream);
 
 __global__ void k_init_product(MpsView st, const uint8_t* occ);

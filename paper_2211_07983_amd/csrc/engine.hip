@@ -254,15 +254,59 @@ void DevHamiltonian::upload_from(const mps_paulisum* h, int N, int dcap, hipStre
   N_ = N;
 }
 
-void mps_ctx::ensure_sweep(int N, int dcap, int chunk) {
+void mps_ctx::ensure_sweep(int N, int dcap, int chunk, int precision) {
   const size_t dd = (size_t)dcap * dcap;
+  // the FP64 identity environments also serve the gradient and hold Z
   sb.Lid = (zd*)b_Lid.ensure((N + 1) * dd * sizeof(zd));
   sb.Rid = (zd*)b_Rid.ensure((N + 1) * dd * sizeof(zd));
-  sb.Lslots = (zd*)b_Lslots.ensure((size_t)chunk * dd * sizeof(zd));
-  sb.Y = (zd*)b_Y.ensure((size_t)chunk * 2 * dd * sizeof(zd));
-  sb.Yid = (zd*)b_Yid.ensure(2 * dd * sizeof(zd));
+  if (precision == 0) {
+    sb.Lslots = (zd*)b_Lslots.ensure((size_t)chunk * dd * sizeof(zd));
+    sb.Y = (zd*)b_Y.ensure((size_t)chunk * 2 * dd * sizeof(zd));
+    sb.Yid = (zd*)b_Yid.ensure(2 * dd * sizeof(zd));
+  } else {
+    s32.B = (cf*)b_B32.ensure((size_t)N * 2 * dd * sizeof(cf));
+    s32.Lid = (cf*)b_Lid32.ensure((N + 1) * dd * sizeof(cf));
+    s32.Rid = (cf*)b_Rid32.ensure((N + 1) * dd * sizeof(cf));
+    s32.Lslots = (cf*)b_Lslots32.ensure((size_t)chunk * dd * sizeof(cf));
+    s32.Y = (cf*)b_Y32.ensure((size_t)chunk * 2 * dd * sizeof(cf));
+    s32.Yid = (cf*)b_Yid32.ensure(2 * dd * sizeof(cf));
+  }
   sb.energy = (double*)b_energy.ensure(8 * sizeof(double));
   sb.chunk = chunk;
+}
+
+// S5 with FP32 matrix-core transfers (precision 1); Z is written where the
+// FP64 energy sum reads it.
+static void run_energy_f32(mps_state* st, DevHamiltonian& H) {
+  mps_ctx* ctx = st->ctx;
+  hipStream_t s = ctx->stream;
+  MpsView v = view_of(st);
+  Sweep32& s32 = ctx->s32;
+  HIPCHK(hipMemsetAsync(s32.Lid, 0, ctx->b_Lid32.bytes, s));
+  HIPCHK(hipMemsetAsync(s32.Rid, 0, ctx->b_Rid32.bytes, s));
+  HIPCHK(launch_sites_f32(v, s32.B, s));
+  HIPCHK(launch_identity_envs_f32(v, s32, s));
+  for (auto& ch : H.chunks) {
+    for (int n = ch.lo; n <= ch.hi; ++n) {
+      const SiteList& sl = ch.sites[n - ch.lo];
+      if (sl.njobs) HIPCHK(launch_transfer_f32(v, s32, n, H.d_jobs_ptr + sl.job_off, sl.njobs, s));
+      if (sl.nfin)
+        HIPCHK(launch_finalize_f32(v, s32, ctx->sb.termval, n, H.d_fin_slot_ptr + sl.fin_off,
+                                   H.d_fin_term_ptr + sl.fin_off, sl.nfin, s));
+    }
+  }
+  HIPCHK(launch_norm_from_f32(v, s32, ctx->sb.Lid + (size_t)st->N * st->dcap * st->dcap, s));
+  HIPCHK(launch_energy_sum(v, ctx->sb, H.d_coeff_ptr, H.K, H.c0, s));
+}
+
+// FP64 identity environments of a state (the sweep adjoint's inputs).
+void run_identity_envs(mps_state* st) {
+  mps_ctx* ctx = st->ctx;
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipMemsetAsync(ctx->sb.Lid, 0, ctx->b_Lid.bytes, s));
+  HIPCHK(hipMemsetAsync(ctx->sb.Rid, 0, ctx->b_Rid.bytes, s));
+  MpsView v = view_of(st);
+  HIPCHK(launch_identity_envs(v, ctx->sb, s));
 }
 
 // Runs S5-S6 on a state: identity environments, every term, the energy sum.
@@ -270,8 +314,12 @@ void run_energy(mps_state* st, DevHamiltonian& H) {
   mps_ctx* ctx = st->ctx;
   hipStream_t s = ctx->stream;
   const int dc = st->dcap;
-  ctx->ensure_sweep(st->N, dc, H.chunk);
+  ctx->ensure_sweep(st->N, dc, H.chunk, st->trunc.precision);
   ctx->sb.termval = (zd*)ctx->b_termval.ensure(std::max<int64_t>(1, H.K) * sizeof(zd));
+  if (st->trunc.precision == 1) {
+    run_energy_f32(st, H);
+    return;
+  }
   HIPCHK(hipMemsetAsync(ctx->sb.Lid, 0, ctx->b_Lid.bytes, s));
   HIPCHK(hipMemsetAsync(ctx->sb.Rid, 0, ctx->b_Rid.bytes, s));
   MpsView v = view_of(st);
@@ -412,6 +460,7 @@ mps_status mps_init_product(mps_ctx* ctx, int32_t n_qubits, const uint8_t* occ_b
     if (!occ_bits || !trunc) fail(MPS_EINVAL, "NULL argument");
     if (trunc->d_max < 1 || trunc->d_max > 256) fail(MPS_EINVAL, "d_max must be in [1, 256]");
     if (!(trunc->eps >= 0.0) || !std::isfinite(trunc->eps)) fail(MPS_EINVAL, "eps must be finite and >= 0");
+    if (trunc->precision != 0 && trunc->precision != 1) fail(MPS_EINVAL, "precision must be 0 or 1");
     for (int q = 0; q < n_qubits; ++q)
       if (occ_bits[q] > 1) fail(MPS_EINVAL, "occupation bits must be 0 or 1");
     mps_state* st = new mps_state();

@@ -140,6 +140,7 @@ mps_status mps_plan_create(mps_ctx* ctx, const uint8_t* occ_bits, const mps_circ
     if (N < 2 || N > 64) fail(MPS_EINVAL, "n_qubits must be in [2, 64]");
     if (trunc->d_max < 1 || trunc->d_max > 256) fail(MPS_EINVAL, "d_max must be in [1, 256]");
     if (!(trunc->eps >= 0.0) || !std::isfinite(trunc->eps)) fail(MPS_EINVAL, "eps must be finite and >= 0");
+    if (trunc->precision != 0 && trunc->precision != 1) fail(MPS_EINVAL, "precision must be 0 or 1");
     for (int q = 0; q < N; ++q)
       if (occ_bits[q] > 1) fail(MPS_EINVAL, "occupation bits must be 0 or 1");
     mps_plan* p = new mps_plan();

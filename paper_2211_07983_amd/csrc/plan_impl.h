@@ -34,6 +34,7 @@ void alloc_state(mps_state* st);
 void init_product(mps_state* st, const uint8_t* occ_dev);
 void copy_state(mps_state* dst, mps_state* src, hipStream_t s);
 void run_energy(mps_state* st, DevHamiltonian& H);
+void run_identity_envs(mps_state* st);
 // Applies gates [g0, g1).  A plan's forward pass uses GATE_TAPE so that the
 // states it checkpoints are bitwise the ones its reverse pass recomputes.
 void run_gates(mps_state* st, DevCircuit& C, const double* theta_dev, int g0, int g1, GateMode mode);
