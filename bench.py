@@ -157,6 +157,46 @@ def cpu_baseline_sample(prob, gates, eps, budget_s=25.0):
             "seconds_per_eval": per_eval}
 
 
+# HBM traffic per launch of the dominant kernels, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE) of the default commands, each scaled by what the
+# counter reads for a 1 GiB device copy in the same run (FETCH_SIZE reads 0.5 GiB
+# for it: factor 2.0; WRITE_SIZE reads 1 GiB: factor 1.0).  Keyed by the SHA-256
+# prefix of the kernel source the counters were taken on: a changed source
+# reports null.
+TRAFFIC = {
+    ("evalgrad", "c2"): {"source": "paper_2211_07983_amd/csrc/gate.hip", "sha": "87f58631c2e081d2",
+                         "fetch_bytes": 132.75e9, "write_bytes": 169.49e9,
+                         "per": "forward launch of k_chain_lanes<16>, 64 lanes x 512 gates"},
+    ("sweep", "c3"): {"source": "paper_2211_07983_amd/csrc/sweep32.hip", "sha": "2b6a464e9cd741ba",
+                      "fetch_bytes": 276.68e9, "write_bytes": 106.78e9,
+                      "per": "one sweep (all k_left1_f32 + k_left2_f32 dispatches)"},
+}
+
+
+def traffic_for(phase, workload):
+    import hashlib
+    t = TRAFFIC.get((phase, workload))
+    if t is None:
+        return None, None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha"]:
+            return None, None
+    return t["fetch_bytes"] + t["write_bytes"], t
+
+
+def calibration_copy(mib):
+    """One elementwise device copy of `mib` MiB (reads and writes mib MiB)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {mib} MiB read, {mib} MiB written")
+    del src, dst
+
+
 def sweep_cmacs(dims, hx, hz):
     """Complex multiply-adds of one sweep: every (term, site) transfer is two
     GEMMs, a*a*2b + 2a*b*b = 2ab(a+b) with a, b the bonds left and right of the
@@ -221,7 +261,7 @@ def sweep_phase(args):
                    "energy_error_ha": abs(res[1]["E"] - res[0]["E"]), "E_fp64": res[0]["E"]},
         "roofline": {"kernel": "k_left1_f32 + k_left2_f32 (whole sweep phase)", "bound": "mfma",
                      "achieved": eff, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": eff / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                     "frac": eff / PEAK_FP32_MFMA_TFLOPS, "traffic": traffic_for("sweep", args.workload)[0],
                      "issued_tflops": 0.75 * eff, "cmac_per_sweep": cmac,
                      "fp64_achieved": 8.0 * cmac / (res[0]["ms"] * 1e-3) / 1e12},
         "cpu_baseline": None,
@@ -244,12 +284,17 @@ def main():
     ap.add_argument("--phase", choices=["evalgrad", "sweep"], default="evalgrad")
     ap.add_argument("--prefix-gates", type=int, default=3000,
                     help="--phase sweep: gates applied before the sweeps are timed")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a reference "
+                         "dispatch of known traffic for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the hot path runs on a single GPU in this build "
               "(the multi-GPU split is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.calibrate_copy_mib > 0:
+        calibration_copy(args.calibrate_copy_mib)
     if args.phase == "sweep":
         sweep_phase(args)
         return
@@ -311,7 +356,8 @@ def main():
     achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12 if n_svd else None
     roofline = {"kernel": f"k_chain_lanes<{W}>" if nb > 1 else f"k_svd_jacobi<{W}, true>", "bound": "alu",
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": None,
+                "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
+                "traffic": traffic_for("evalgrad", args.workload)[0] if nb == 64 else None,
                 "avg_launch_ms": avg_ms, "flop_per_launch": flop_per_launch, "timed_launches": n_svd}
     cpu = None
     if not args.no_cpu_baseline:
