@@ -61,7 +61,14 @@ typedef struct mps_plan mps_plan;
 
 /* Truncation of every two-qubit update (Sec. 3): keep
  * r = min(d_max, #{s_i > eps}) >= 1 Schmidt values of the normalised state
- * and renormalise them.  precision: 0 = FP64 everywhere.                     */
+ * and renormalise them.
+ * precision: 0 = FP64 everywhere.  1 = the Pauli sweep's transfers (Sec. 3,
+ *   Eq. paulistringexp: identity environments and every term's left
+ *   transfers) run as complex FP32 products on the matrix cores with FP32
+ *   accumulation; the term inner products, Z and the energy sum stay FP64, as
+ *   do the gates (contraction, SVD, update) and the whole reverse pass.  The
+ *   energy is then accurate to about 1e-7 relative per term value.  Any other
+ *   value gives MPS_EINVAL.                                                   */
 typedef struct {
   int32_t d_max;
   double eps;
