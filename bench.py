@@ -49,6 +49,7 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 (vector and matrix): 256 CU x 2.4 GHz 
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix: 256 CU x 2.4 GHz x 256 flop/clk
 METRIC = "energy+grad evals/s (UCCSD-MPS 24q D=128) vs plain FP64; MFMA util %"
 WORKLOADS = {
+    "c1": "UCCSD-MPS 8 qubits (4 orbitals, 4 electrons), D=16",
     "c3": "UCCSD-MPS 24 qubits (12 orbitals, 12 electrons), D=128",
     "c2": "UCCSD-MPS 14 qubits (7 orbitals, 10 electrons), D=64",
 }
@@ -269,6 +270,41 @@ def sweep_phase(args):
     print(json.dumps(line), flush=True)
 
 
+def psr_phase(args):
+    """Gradient by the parameter-shift rule (2M + 1 batched forward evaluations)
+    against back-propagation (one forward + reverse pass) on the same plan."""
+    import numpy as np
+    from vqe_inputs import configs
+    from paper_2211_07983_amd import Context, Plan
+    prob, gates = configs.load(args.workload, eps=args.eps)
+    ctx = Context(0)
+    plan = Plan(ctx, prob.occ, gates, prob.n_qubits, prob.ham_x, prob.ham_z, prob.ham_c, prob.c0,
+                prob.bond_dim, prob.eps, ckpt_gates=args.ckpt_gates)
+    M = int((np.asarray(gates.kind) == 1).sum())
+    plan.energy_grad(prob.theta)                       # warm-up
+    t0 = time.perf_counter()
+    e_bp, g_bp, _ = plan.energy_grad(prob.theta)
+    t_bp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e_ps, g_ps, _, st = plan.energy_grad_psr(prob.theta)
+    t_ps = time.perf_counter() - t0
+    log(f"back-propagation {t_bp:.3f}s, parameter shift {t_ps:.3f}s ({2 * M + 1} evaluations)")
+    diff = float(np.abs(g_ps - g_bp).max() / max(1e-300, np.abs(g_bp).max()))
+    line = {
+        "metric": "gradient time, parameter shift / back-propagation (same plan, one GPU)",
+        "value": t_ps / t_bp, "unit": "ratio", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * t_ps, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload] + f", eps={prob.eps:g}, {gates.n_gates} NN gates, "
+                               f"M={M} parametric gates, n_theta={prob.n_theta}",
+                   "t_backprop_s": t_bp, "t_psr_s": t_ps, "psr_evaluations": 2 * M + 1,
+                   "psr_lanes_per_launch": plan.lanes_per_launch(),
+                   "max_rel_grad_diff": diff, "E": e_bp},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,7 +317,7 @@ def main():
     ap.add_argument("--ckpt-gates", type=int, default=512)
     ap.add_argument("--profile-every", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phase", choices=["evalgrad", "sweep"], default="evalgrad")
+    ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr"], default="evalgrad")
     ap.add_argument("--prefix-gates", type=int, default=3000,
                     help="--phase sweep: gates applied before the sweeps are timed")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -297,6 +333,9 @@ def main():
         calibration_copy(args.calibrate_copy_mib)
     if args.phase == "sweep":
         sweep_phase(args)
+        return
+    if args.phase == "psr":
+        psr_phase(args)
         return
     import numpy as np
     from vqe_inputs import configs
@@ -362,7 +401,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         with one_thread():
-            if args.workload == "c2":
+            if args.workload in ("c1", "c2"):
                 cpu = cpu_baseline_full(prob, gates, prob.eps)
             else:
                 cpu = cpu_baseline_sample(prob, gates, prob.eps)

@@ -189,9 +189,10 @@ mps_status mps_energy_grad(mps_plan* plan, const double* theta, int32_t n_theta,
  * parameter vectors thetas[b][:] of the same plan (row-major [n_batch][n_theta];
  * host arrays, or device addresses for thetas and grads when
  * theta_on_device != 0; energies is always host).  The vectors go through the
- * circuit together: each gate step is one launch per kernel for all of them
- * (as many as fit the device at once; larger batches run in groups), so the
- * compute units that a single evaluation's SVD chain leaves idle are used.
+ * circuit together: each checkpoint segment is one launch of the gate-chain
+ * kernel for all of them (as many as fit the device at once; larger batches
+ * run in groups), so the compute units that a single evaluation's SVD chain
+ * leaves idle are used.
  * Every result equals the one of mps_energy_grad on that vector alone.
  * stats: sums over the batch (truncation, bonds, sweeps) and the wall time of
  * the whole call in t_backward_ms.                                          */
@@ -203,6 +204,22 @@ mps_status mps_energy_grad_batched(mps_plan* plan, int32_t n_batch, const double
  * each vector occupies ceil(2 d_max / (2 W)) compute units); larger batches
  * run in groups of this size.  Returns <= 0 on error.                      */
 int32_t mps_plan_batch_width(mps_plan* plan);
+
+/* Parameter-shift gradient (Sec. 4, Eq. psr) of the plan's energy, the
+ * baseline that mps_energy_grad's back-propagation replaces.  For each PARAM
+ * gate g (angle phi_g = coeff[g] theta[param[g]]; RZZ(phi) = exp(-i phi ZZ/2),
+ * generator eigenvalues +-1/2) the energy is evaluated with phi_g shifted by
+ * +pi/2 and by -pi/2: dE/dphi_g = (E+ - E-)/2, and
+ * grad[p] = sum over gates g with param[g] = p of coeff[g] dE/dphi_g.
+ * 2M + 1 forward evaluations for M PARAM gates, run as lanes of batched
+ * launches of the gate-chain kernel (mps_plan_batch_width per launch).
+ * theta, grad: host [n_theta]; energy: E(theta); gate_grad (nullable): host
+ * [n_gates], dE/dphi_g for PARAM gates and 0 for FIXED ones.  Without
+ * truncation the result equals the back-propagated gradient; with it, each
+ * shifted evaluation truncates on its own.  stats: sums over all evaluations,
+ * the wall time in t_gates_ms.  Errors as mps_energy_grad.                  */
+mps_status mps_energy_grad_psr(mps_plan* plan, const double* theta, int32_t n_theta, double* energy,
+                               double* grad, double* gate_grad, mps_stats* stats);
 
 /* Forward pass of a plan only (energy at theta, no gradient).              */
 mps_status mps_plan_energy(mps_plan* plan, const double* theta, int32_t n_theta,

@@ -220,6 +220,7 @@ class Plan:
                                            C.byref(tr), C.byref(go), C.byref(h)))
         self.h = h
         self.n_theta = int(np.max(gates.param)) + 1 if np.any(np.asarray(gates.kind) == 1) else 0
+        self.n_gates = len(gates.bond)
         _live_children.add(self)
 
     def energy(self, theta):
@@ -278,6 +279,18 @@ class Plan:
             self.h, nb, th.ctypes.data_as(C.c_void_p), th.shape[1], 0, _ptr(e, C.c_double),
             g.ctypes.data_as(C.c_void_p), C.byref(s)))
         return e, g, s.as_dict()
+
+    def energy_grad_psr(self, theta):
+        """Parameter-shift gradient: (E, grad [n_theta], dE/dphi per gate [n_gates], stats)."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        e = C.c_double()
+        g = np.zeros(max(1, len(th)))
+        gg = np.zeros(max(1, self.n_gates))
+        s = Stats()
+        self.ctx.check(self.ctx._lib.mps_energy_grad_psr(self.h, _ptr(th, C.c_double) if len(th) else None, len(th),
+                                                         C.byref(e), _ptr(g, C.c_double), _ptr(gg, C.c_double),
+                                                         C.byref(s)))
+        return e.value, g[:len(th)], gg[:self.n_gates], s.as_dict()
 
     def free(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):

@@ -1115,6 +1115,8 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
       ln.bar = lane_bars + l;
       ln.err = lane_err;
       ln.ckpt = nullptr;
+      ln.shift_gate = -1;
+      ln.shift = 0.0;
       steps = std::max(steps, ln.ng);
     }
     HIPCHK(hipMemcpyAsync(lanes_d, p->lanes_h.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
@@ -1268,6 +1270,8 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
     ln.bar = lane_bars + l;
     ln.err = lane_err;
     ln.theta = thetas_dev + (size_t)l * nth;
+    ln.shift_gate = -1;
+    ln.shift = 0.0;
   }
   LaneConst lc;
   lc.gt = p->C.tab;
@@ -1488,6 +1492,152 @@ void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_t
       stats->prof_svd_flop = gsum.svd_flop;
       stats->prof_svd_launches = prof_n;
     }
+  }
+}
+
+// ============================================================================
+// Parameter-shift gradient (Sec. 4, Eq. psr).  RZZ(phi) = exp(-i phi ZZ/2) has
+// generator eigenvalues +-1/2, so for every PARAM gate g
+//   dE/dphi_g = (E(phi_g + pi/2) - E(phi_g - pi/2)) / 2,
+// and dE/dtheta_p = sum over the gates of p of coeff_g dE/dphi_g.  The 2M + 1
+// evaluations (the unshifted one first, then +pi/2 and -pi/2 for each PARAM
+// gate in circuit order) are lanes of the gate-chain kernel, as many per
+// launch as fit; each lane's energy is then swept on its own.
+// ============================================================================
+void plan_energy_grad_psr(mps_plan* p, const double* theta, int n_theta, double* energy, double* grad,
+                          double* gate_grad, mps_stats* stats) {
+  mps_ctx* ctx = p->ctx;
+  hipStream_t s = ctx->stream;
+  if (n_theta != p->n_theta) fail(MPS_EINVAL, "n_theta does not match the circuit");
+  if (n_theta > 0 && !theta) fail(MPS_EINVAL, "NULL theta");
+  validate_theta(theta, n_theta);
+  const int N = p->N, G = p->C.G, K = p->opts.ckpt_gates;
+  const int dc = p->state->dcap;
+  ctx->ensure_gate_work(dc, p->trunc, p->opts.max_sweeps);
+  const GateWork gw = ctx->gw;
+  const TapeLayout L = tape_layout(dc, gw.ncap, gw.ldc, gw.ldv);
+  std::vector<int> pg;
+  for (int g = 0; g < G; ++g)
+    if (p->C.kind_h[g] == 1) pg.push_back(g);
+  const int M = (int)pg.size(), nev = 2 * M + 1;
+  BatchSet& B = batch_of(p);
+  double* th = (double*)B.thetas.ensure((size_t)std::max(1, n_theta) * sizeof(double));
+  if (n_theta > 0) HIPCHK(hipMemcpyAsync(th, theta, (size_t)n_theta * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int nmax = std::min(lanes_max(dc), nev);
+  while ((int)B.lanes.size() < nmax) {
+    BatchLane* bl = new BatchLane();
+    B.lanes.push_back(bl);
+    bl->st = plan_new_state(ctx, N, p->trunc, nullptr);
+    bl->rp = plan_new_state(ctx, N, p->trunc, nullptr);
+  }
+  const size_t aux_lane = 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats) + 64;
+  const size_t aux_bytes = (size_t)nmax * aux_lane + 64 + (size_t)nmax * 8;
+  char* aux = (char*)B.aux.ensure(aux_bytes);
+  int* lane_err = (int*)(aux + (size_t)nmax * aux_lane);
+  unsigned long long* lane_bars = (unsigned long long*)(aux + (size_t)nmax * aux_lane + 64);
+  char* tape = (char*)B.tape.ensure((size_t)nmax * L.rec);   // one record per lane, reused by every step
+  GateLane* lanes_d = (GateLane*)B.lanes_dev.ensure((size_t)nmax * sizeof(GateLane));
+  LaneConst lc;
+  lc.gt = p->C.tab;
+  lc.L = L;
+  lc.ldc = gw.ldc;
+  lc.ldv = gw.ldv;
+  lc.ncap = gw.ncap;
+  lc.dmax = gw.dmax;
+  lc.max_sweeps = gw.max_sweeps;
+  lc.nparts = ((2 * dc + ZT_M - 1) / ZT_M) * ((2 * dc + ZT_M - 1) / ZT_M);
+  lc.eps = gw.eps;
+  lc.tol = gw.tol;
+  lc.ck_B = lc.ck_dims = lc.ck_lam = 0;
+  std::vector<double> E(nev);
+  std::vector<GateLane> lh(nmax);
+  std::vector<GateStats> st(nmax);
+  GateStats gsum{};
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  HIPCHK(hipEventRecord(t0, s));
+  for (int e0 = 0; e0 < nev; e0 += nmax) {
+    const int nl = std::min(nmax, nev - e0);
+    HIPCHK(hipMemsetAsync(aux, 0, aux_bytes, s));
+    for (int l = 0; l < nl; ++l) {
+      const int ev = e0 + l;
+      BatchLane* bl = B.lanes[l];
+      init_product(bl->st, (const uint8_t*)p->state->occ.p);
+      GateLane ln{};
+      ln.st = view_of(bl->st);
+      ln.rec_stride = 0;
+      ln.theta = th;
+      ln.ckpt = nullptr;
+      ln.tape = tape + (size_t)l * L.rec;
+      char* la = aux + (size_t)l * aux_lane;
+      ln.rotflag = (int*)la;
+      ln.nrm_part = (double*)(la + 128 * sizeof(int));
+      ln.stats = (GateStats*)(la + 128 * sizeof(int) + 256 * sizeof(double));
+      ln.bar = lane_bars + l;
+      ln.err = lane_err;
+      ln.shift_gate = ev == 0 ? -1 : pg[(ev - 1) / 2];
+      ln.shift = ev == 0 ? 0.0 : ((ev - 1) % 2 == 0 ? 0.5 * M_PI : -0.5 * M_PI);
+      lh[l] = ln;
+    }
+    for (int g0 = 0; g0 < G; g0 += K) {
+      for (int l = 0; l < nl; ++l) {
+        lh[l].g0 = g0;
+        lh[l].ng = std::min(G, g0 + K) - g0;
+      }
+      HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
+      HIPCHK(launch_chain_lanes(lanes_d, nl, lc, false, lane_bars, s));
+      HIPCHK(hipStreamSynchronize(s));   // lh is rewritten for the next segment
+    }
+    int err = 0;
+    HIPCHK(hipMemcpyAsync(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    for (int l = 0; l < nl; ++l)
+      HIPCHK(hipMemcpyAsync(&st[l], lh[l].stats, sizeof(GateStats), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (err) fail(MPS_EDEVICE, "a lane barrier of the parameter-shift evaluations timed out");
+    for (int l = 0; l < nl; ++l) {
+      const GateStats& x = st[l];
+      gsum.disc_sum += x.disc_sum;
+      gsum.disc_max = std::max(gsum.disc_max, x.disc_max);
+      gsum.truncated += x.truncated;
+      gsum.max_sweeps = std::max(gsum.max_sweeps, x.max_sweeps);
+      gsum.noconv += x.noconv;
+      gsum.degenerate_cuts += x.degenerate_cuts;
+      gsum.max_bond = std::max(gsum.max_bond, x.max_bond);
+      gsum.gates += x.gates;
+      run_energy(B.lanes[l]->st, p->H);
+      double ev[3];
+      HIPCHK(hipMemcpyAsync(ev, ctx->sb.energy, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      E[e0 + l] = ev[0];
+    }
+    if (ctx->progress) ctx->progress(ctx->progress_user, "parameter shift", std::min(nev, e0 + nl), nev);
+  }
+  HIPCHK(hipEventRecord(t1, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (gsum.noconv) fail(MPS_ENOCONV, "Jacobi SVD did not converge in " + std::to_string(p->opts.max_sweeps) + " sweeps");
+  std::vector<double> gg(std::max(1, G), 0.0);
+  for (int i = 0; i < M; ++i) gg[pg[i]] = 0.5 * (E[1 + 2 * i] - E[2 + 2 * i]);
+  for (int q = 0; q < n_theta; ++q) grad[q] = 0.0;
+  for (int i = 0; i < M; ++i) grad[p->C.param_h[pg[i]]] += p->C.coeff_h[pg[i]] * gg[pg[i]];
+  if (gate_grad)
+    for (int g = 0; g < G; ++g) gate_grad[g] = gg[g];
+  *energy = E[0];
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->discarded_weight_sum = gsum.disc_sum;
+    stats->discarded_weight_max = gsum.disc_max;
+    stats->max_bond = gsum.max_bond;
+    stats->gates_truncated = gsum.truncated;
+    stats->max_sweeps_used = gsum.max_sweeps;
+    stats->degenerate_cuts = gsum.degenerate_cuts;
+    stats->n_gates_applied = gsum.gates;
+    stats->t_gates_ms = ms;
   }
 }
 

@@ -76,7 +76,8 @@ struct SvdArgs {
 // ----------------------------------------------------------------------------
 // Gate matrix Q (4x4) of gate g, evaluated on the device from theta.
 // ----------------------------------------------------------------------------
-__device__ inline void gate_matrix(const GateTable& gt, int g, const double* theta, zd* Q) {
+// dphi is added to a PARAM gate's angle (the parameter-shift evaluations).
+__device__ inline void gate_matrix(const GateTable& gt, int g, const double* theta, zd* Q, double dphi = 0.0) {
   // called by threads 0..15 of a block, Q in shared memory
   const int t = threadIdx.x;
   const zd* pre = gt.pre + (size_t)g * 16;
@@ -85,7 +86,7 @@ __device__ inline void gate_matrix(const GateTable& gt, int g, const double* the
     return;
   }
   const zd* post = gt.post + (size_t)g * 16;
-  const double phi = gt.coeff[g] * theta[gt.param[g]];
+  const double phi = gt.coeff[g] * theta[gt.param[g]] + dphi;
   double sn, cs;
   sincos(0.5 * phi, &sn, &cs);
   // RZZ diagonal: e^{-i phi/2}, e^{+i phi/2}, e^{+i phi/2}, e^{-i phi/2}
@@ -126,6 +127,8 @@ struct GateLane {
   double* nrm_part;   // [256] |C~|^2 partial sums
   unsigned long long* bar;   // lane barrier counter
   int* err;           // set when a lane barrier timed out
+  int shift_gate;     // gate whose angle is shifted by `shift` (-1: none)
+  double shift;
 };
 
 // Launch constants shared by all lanes.

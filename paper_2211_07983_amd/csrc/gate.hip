@@ -23,7 +23,8 @@
 // GEMM (ZT_LDS_ELEMS elements), or nullptr for the kernel's own.
 template <bool DYN>
 __device__ void contract_tile(const MpsView& st, const GateTable& gt, int g, const double* theta, zd* C, zd* A,
-                              int ldc, double* nrm_part, int trans, int bx, int by, int nbx, zd* sbuf) {
+                              int ldc, double* nrm_part, int trans, int bx, int by, int nbx, zd* sbuf,
+                              double dphi = 0.0) {
   __shared__ zd Q[16];
   __shared__ double red[256];
   const int n = gt.bond[g];
@@ -35,7 +36,7 @@ __device__ void contract_tile(const MpsView& st, const GateTable& gt, int g, con
     if (threadIdx.x == 0) nrm_part[part] = 0.0;
     return;
   }
-  gate_matrix(gt, g, theta, Q);
+  gate_matrix(gt, g, theta, Q, dphi);
   const zd* Bl = st.site(n);
   const zd* Br = st.site(n + 1);
   const int dc = st.dcap;
@@ -684,7 +685,7 @@ __global__ __launch_bounds__(256) void k_chain_lanes(const GateLane* lanes, Lane
     if (p == 0 && threadIdx.x < 128) ln.rotflag[threadIdx.x] = 0;
     for (int tile = p; tile < tiles * tiles; tile += nblk)
       contract_tile<true>(st, c.gt, g, ln.theta, R.C, R.A, c.ldc, ln.nrm_part, 0, tile % tiles, tile / tiles, tiles,
-                          sbuf);
+                          sbuf, g == ln.shift_gate ? ln.shift : 0.0);
     bar.sync();
     const SvdArgs s = lane_svd_args(ln, c, n, R);
     svd_body<W, true>(s, p, nblk, bar);

@@ -195,6 +195,12 @@ mps_status mps_energy_grad_batched(mps_plan* plan, int32_t n_batch, const double
   });
 }
 
+mps_status mps_energy_grad_psr(mps_plan* plan, const double* theta, int32_t n_theta, double* energy, double* grad,
+                               double* gate_grad, mps_stats* stats) {
+  if (!plan || !energy || (plan->n_theta > 0 && !grad)) return MPS_EINVAL;
+  return guarded(plan->ctx, [&] { plan_energy_grad_psr(plan, theta, n_theta, energy, grad, gate_grad, stats); });
+}
+
 int32_t mps_plan_batch_width(mps_plan* plan) {
   if (!plan) return MPS_EINVAL;
   int32_t w = 0;

@@ -46,5 +46,7 @@ mps_state* plan_new_state(mps_ctx* ctx, int N, const mps_trunc& tr, const uint8_
 void plan_forward_energy(mps_plan* p, const double* theta, int n_theta, int on_device, double* energy,
                          mps_stats* stats, bool keep_checkpoints);
 void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats);
+void plan_energy_grad_psr(mps_plan* p, const double* theta, int n_theta, double* energy, double* grad,
+                          double* gate_grad, mps_stats* stats);
 void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_theta, int on_device,
                               double* energies, double* grads, mps_stats* stats);
