@@ -936,8 +936,9 @@ static void build_chain(mps_plan* p, PlanAdj& A) {
     list.insert(list.end(), per[q].begin(), per[q].end());
   }
   start[p->n_theta] = (int)list.size();
+  if (list.empty()) list.push_back(0);   // no PARAM gates: a one-entry placeholder, never read
   upload(A.chain_start, start.data(), start.size(), p->ctx->stream);
-  upload(A.chain_list, list.data(), std::max<size_t>(1, list.size()), p->ctx->stream);
+  upload(A.chain_list, list.data(), list.size(), p->ctx->stream);
   A.chain_built = true;
 }
 
@@ -1169,8 +1170,9 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   }
   if (!A.chain_built) build_chain(p, A);
   double* gd_dev = (double*)p->grad.ensure((size_t)std::max(1, p->n_theta) * sizeof(double));
-  hipLaunchKernelGGL(k_chain_rule, dim3((p->n_theta + 255) / 256), dim3(256), 0, s, (const int*)A.chain_start.p,
-                     (const int*)A.chain_list.p, p->C.tab, (const double*)gphi, gd_dev, p->n_theta);
+  if (p->n_theta > 0)
+    hipLaunchKernelGGL(k_chain_rule, dim3((p->n_theta + 255) / 256), dim3(256), 0, s, (const int*)A.chain_start.p,
+                       (const int*)A.chain_list.p, p->C.tab, (const double*)gphi, gd_dev, p->n_theta);
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(e1, s));
   if (p->n_theta > 0)
@@ -1415,7 +1417,7 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
   // ---- chain rule per lane
   PlanAdj& A = adj_of(p);
   if (!A.chain_built) build_chain(p, A);
-  for (int l = 0; l < nl; ++l)
+  for (int l = 0; l < nl && p->n_theta > 0; ++l)
     hipLaunchKernelGGL(k_chain_rule, dim3((p->n_theta + 255) / 256), dim3(256), 0, s,
                        (const int*)A.chain_start.p, (const int*)A.chain_list.p, p->C.tab,
                        (const double*)B.lanes[l]->gphi.p, grads_dev + (size_t)l * nth, p->n_theta);
