@@ -220,13 +220,15 @@ struct LaneBarrier {
   unsigned long long nblk;
   unsigned long long gen;
   __device__ void sync() {
-    // every wave's stores of the phase written back before the arrival (the
-    // work-group barrier alone does not wait for global stores)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // every wave's global stores of the phase complete (the work-group barrier
+    // alone does not wait for them), then one agent-scope release for the
+    // work-group: a single L2 write-back instead of one per wave
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
       const unsigned long long target = (gen + 1) * nblk;
-      __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // relaxed polls: an acquire load would invalidate the caches on every
       // poll, under every other lane resident on the same L2
       unsigned spins = 0;
