@@ -392,14 +392,18 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
         store_blocks(s.A, s.lda, Al, mpad, M, ncol, W, q0, q1);
         if (ACC) store_blocks(s.V, s.ldv, Vl, vpad, ncol, ncol, W, q0, q1);
       }
+      // Sweep finished with this round: count the work-groups that rotated.
+      // The counter of this sweep (zeroed before the launch) is incremented
+      // before the round's barrier and read after it, so every work-group
+      // reads the same value and all of them leave the loop after the same
+      // number of barriers.
+      if (k == 2 * P - 2) {
+        __syncthreads();   // sh_rot final
+        if (t == 0 && sh_rot)
+          __hip_atomic_fetch_add(&s.rotflag[sweep], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       bar.sync();
     }
-    // Sweep finished: count the work-groups that rotated.  The counter of this
-    // sweep (zeroed before the launch) is only incremented before the barrier
-    // and only read after it, so every work-group reads the same value and all
-    // of them leave the loop after the same number of barriers.
-    if (t == 0 && sh_rot) __hip_atomic_fetch_add(&s.rotflag[sweep], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bar.sync();
     if (t == 0) sh_stop = __hip_atomic_load(&s.rotflag[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     __syncthreads();
     if (sh_stop) break;
