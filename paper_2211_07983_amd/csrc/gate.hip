@@ -250,6 +250,13 @@ struct LaneBarrier {
   }
 };
 
+// LDS column pitch of the Jacobi blocks: the matrix's leading dimension, at
+// least the 8 * 256 / W rows that the 256 threads of a pair group cover.
+__host__ __device__ inline int svd_pitch(int ld, int W) {
+  const int R = 8 * 256 / W;
+  return ld > R ? ld : R;
+}
+
 template <int W, bool ACC, class Barrier>
 __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier& bar) {
   constexpr int TPP = 256 / W;     // threads per column pair
@@ -260,14 +267,22 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
   const int M = s.trans ? 2 * b : 2 * a, ncol = s.trans ? 2 * a : 2 * b;
   const int P = (ncol + 2 * W - 1) / (2 * W);
   const int t = threadIdx.x;
-  const int mpad = s.lda;          // LDS column stride for A
-  const int vpad = s.ldv;          // LDS column stride for V
+  const int mpad = svd_pitch(s.lda, W);   // LDS column stride for A
+  const int vpad = svd_pitch(s.ldv, W);   // LDS column stride for V
   zd* Al = lds;                    // [2W][mpad]
   zd* Vl = lds + 2 * W * mpad;     // [2W][vpad] (ACC only)
   __shared__ int sh_rot;
   __shared__ int sh_stop;
   const int pr = t / TPP, lt = t % TPP;
   const double tol = s.tol;
+  // Rows past the matrix in the LDS blocks hold zeros for the whole call: the
+  // cross rounds rotate all RPT * TPP rows of a pair without bounds checks, and
+  // rotations keep zero rows zero.
+  for (int e = t; e < 2 * W * RPT * TPP; e += 256) {
+    const int c = e / (RPT * TPP), r = e - c * (RPT * TPP);
+    if (r >= M) Al[c * mpad + r] = zmk(0.0, 0.0);
+    if (ACC && r >= ncol) Vl[c * vpad + r] = zmk(0.0, 0.0);
+  }
   // |gamma| below floor = 1e-28 |A|_F^2 means both columns are negligible (far
   // below any kept Schmidt value): such pairs are left alone, which keeps wide
   // matrices, whose surplus columns must shrink to zero, from sweeping forever.
@@ -333,22 +348,22 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
           // cross pairs: column pr of the first block stays in registers
           const int c0 = pr;
           zd xr[RPT], xv[RPT];
+          const zd* xa = Al + c0 * mpad + lt;
+          const zd* xva = Vl + c0 * vpad + lt;
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
-            const int r = lt + i * TPP;
-            xr[i] = r < M ? Al[c0 * mpad + r] : zmk(0.0, 0.0);
-            if (ACC) xv[i] = r < ncol ? Vl[c0 * vpad + r] : zmk(0.0, 0.0);
+            xr[i] = xa[i * TPP];
+            if (ACC) xv[i] = xva[i * TPP];
           }
           for (int sub = 0; sub < W; ++sub) {
-            const int c1 = W + (pr + sub) % W;
-            zd* y = Al + c1 * mpad;
+            const int c1 = W + ((pr + sub) & (W - 1));
+            zd* y = Al + c1 * mpad + lt;
             zd yr[RPT];
             double al0 = 0.0, be0 = 0.0, gr0 = 0.0, gi0 = 0.0, al1 = 0.0, be1 = 0.0, gr1 = 0.0, gi1 = 0.0;
 #pragma unroll
             for (int i = 0; i < RPT; i += 2) {
-              const int r0 = lt + i * TPP, r1 = r0 + TPP;
-              yr[i] = r0 < M ? y[r0] : zmk(0.0, 0.0);
-              yr[i + 1] = r1 < M ? y[r1] : zmk(0.0, 0.0);
+              yr[i] = y[i * TPP];
+              yr[i + 1] = y[(i + 1) * TPP];
               pair_acc(xr[i], yr[i], al0, be0, gr0, gi0);
               pair_acc(xr[i + 1], yr[i + 1], al1, be1, gr1, gi1);
             }
@@ -359,21 +374,17 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
             if (jacobi_rotation(al, be, gr, gi, tol, floor_g, c, pp, qq)) {
 #pragma unroll
               for (int i = 0; i < RPT; ++i) {
-                const int r = lt + i * TPP;
                 const zd u = xr[i], v = yr[i];
                 xr[i] = rot_x(u, v, c, pp);
-                if (r < M) y[r] = rot_y(u, v, c, qq);
+                y[i * TPP] = rot_y(u, v, c, qq);
               }
               if (ACC) {
-                zd* yv = Vl + c1 * vpad;
+                zd* yv = Vl + c1 * vpad + lt;
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
-                  const int r = lt + i * TPP;
-                  if (r < ncol) {
-                    const zd u = xv[i], v = yv[r];
-                    xv[i] = rot_x(u, v, c, pp);
-                    yv[r] = rot_y(u, v, c, qq);
-                  }
+                  const zd u = xv[i], v = yv[i * TPP];
+                  xv[i] = rot_x(u, v, c, pp);
+                  yv[i * TPP] = rot_y(u, v, c, qq);
                 }
               }
               rot = true;
@@ -382,9 +393,8 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
           }
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
-            const int r = lt + i * TPP;
-            if (r < M) Al[c0 * mpad + r] = xr[i];
-            if (ACC && r < ncol) Vl[c0 * vpad + r] = xv[i];
+            Al[c0 * mpad + lt + i * TPP] = xr[i];
+            if (ACC) Vl[c0 * vpad + lt + i * TPP] = xv[i];
           }
           __syncthreads();
         }
@@ -821,7 +831,7 @@ hipError_t launch_contract(const MpsView& st, const GateTable& gt, int g, const 
 
 size_t svd_shared_bytes(int dcap, int ldc, int ldv, GateMode mode) {
   const int W = svd_width(dcap);
-  return (size_t)2 * W * (ldc + (mode == GATE_TAPE ? ldv : 0)) * sizeof(zd);
+  return (size_t)2 * W * (svd_pitch(ldc, W) + (mode == GATE_TAPE ? svd_pitch(ldv, W) : 0)) * sizeof(zd);
 }
 
 hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stream, GateMode mode) {
