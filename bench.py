@@ -318,6 +318,8 @@ def main():
     ap.add_argument("--profile-every", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr"], default="evalgrad")
+    ap.add_argument("--precision", type=int, choices=[0, 1], default=0,
+                    help="evalgrad phase: 0 plain FP64, 1 Pauli sweeps and sweep adjoint on FP32 matrix cores")
     ap.add_argument("--prefix-gates", type=int, default=3000,
                     help="--phase sweep: gates applied before the sweeps are timed")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -356,7 +358,7 @@ def main():
 
     ctx.set_progress(progress)
     plan = Plan(ctx, prob.occ, gates, prob.n_qubits, prob.ham_x, prob.ham_z, prob.ham_c, prob.c0,
-                prob.bond_dim, prob.eps, ckpt_gates=args.ckpt_gates)
+                prob.bond_dim, prob.eps, precision=args.precision, ckpt_gates=args.ckpt_gates)
     nb = args.batch if args.batch > 0 else plan.lanes_per_launch()
     rng = np.random.default_rng(2024)
     thetas = np.stack([prob.theta] + [prob.theta + 0.05 * rng.normal(size=prob.theta.shape) for _ in range(nb - 1)])
@@ -396,7 +398,7 @@ def main():
     roofline = {"kernel": f"k_chain_lanes<{W}>" if nb > 1 else f"k_svd_jacobi<{W}, true>", "bound": "alu",
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
-                "traffic": traffic_for("evalgrad", args.workload)[0] if nb == 64 else None,
+                "traffic": traffic_for("evalgrad", args.workload)[0] if nb == 64 and args.precision == 0 else None,
                 "avg_launch_ms": avg_ms, "flop_per_launch": flop_per_launch, "timed_launches": n_svd}
     cpu = None
     if not args.no_cpu_baseline:
@@ -417,11 +419,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == 0 else "f64 gates, f32-mfma sweeps",
         "data": "synthetic (seeded random integrals, JW Hamiltonian, spin-orbital UCCSD, theta~N(0,0.05); "
                 "batch: that theta and seeded perturbations of 0.05 N(0,1))",
         "config": {"workload": WORKLOADS[args.workload] + f", eps={prob.eps:g}, K={prob.n_terms} Pauli terms, "
-                               f"{gates.n_gates} NN gates, n_theta={prob.n_theta}, plain FP64",
+                               f"{gates.n_gates} NN gates, n_theta={prob.n_theta}, "
+                               + ("plain FP64" if args.precision == 0 else "precision 1 (FP32-MFMA sweeps)"),
                    "global_batch": nb,
                    "single": {"evals_per_s": 1.0 / t_single, "seconds": t_single},
                    "energy": e, "grad_norm": float((g ** 2).sum()) ** 0.5,

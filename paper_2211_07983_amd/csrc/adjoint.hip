@@ -618,6 +618,11 @@ struct SweepAdjPlan {
   const zd* lid = nullptr;   // environment buffers the job pointers refer to
   const zd* rid = nullptr;
   int chunk_slots = 0;
+  // precision 1: the term jobs on FP32 copies of the buffers
+  bool f32 = false;
+  DevBuf Rslots32, Lslots32, Y32, Gb32, d_jobs32, d_inj32;
+  const cf* lid32 = nullptr;
+  const cf* rid32 = nullptr;
 };
 
 struct BatchSet;
@@ -783,6 +788,42 @@ static void build_sweep_adjoint(mps_plan* p, SweepAdjPlan& S, const std::vector<
   upload(S.d_jobs, S.jobs_h.data(), S.jobs_h.size(), ctx->stream);
   upload(S.d_inj, S.inj_h.data(), S.inj_h.size(), ctx->stream);
   S.d_small.ensure(16 * sizeof(EnvJob));
+  // precision 1: the same jobs on FP32 copies of the slot, scratch and identity
+  // environment buffers (a pointer keeps its element offset)
+  S.f32 = p->trunc.precision == 1;
+  if (S.f32) {
+    struct Map {
+      const zd* b64;
+      size_t n;
+      cf* b32;
+    };
+    const Map maps[] = {
+        {Rs, (size_t)std::max(1, max_slots) * dd, (cf*)S.Rslots32.ensure((size_t)std::max(1, max_slots) * dd * sizeof(cf))},
+        {Ls, (size_t)max_terms * dd, (cf*)S.Lslots32.ensure((size_t)max_terms * dd * sizeof(cf))},
+        {Yb, (size_t)max_terms * 2 * dd, (cf*)S.Y32.ensure((size_t)max_terms * 2 * dd * sizeof(cf))},
+        {Gb, (size_t)max_terms * 2 * dd, (cf*)S.Gb32.ensure((size_t)max_terms * 2 * dd * sizeof(cf))},
+        {Lid, (size_t)(N + 1) * dd, ctx->s32.Lid},
+        {Rid, (size_t)(N + 1) * dd, ctx->s32.Rid}};
+    auto tr = [&](const zd* q) -> cf* {
+      if (!q) return nullptr;
+      for (const Map& m : maps)
+        if (q >= m.b64 && q < m.b64 + m.n) return m.b32 + (q - m.b64);
+      fail(MPS_EDEVICE, "sweep adjoint: job pointer outside its buffers");
+      return nullptr;
+    };
+    std::vector<EnvJob32> j32(S.jobs_h.size());
+    for (size_t q = 0; q < S.jobs_h.size(); ++q) {
+      const EnvJob& jb = S.jobs_h[q];
+      j32[q] = EnvJob32{tr(jb.in), tr(jb.out), tr(jb.y), tr(jb.rr), tr(jb.g), jb.c, jb.xb, jb.acc, jb.o0, jb.o1};
+    }
+    std::vector<InjectItem32> i32(S.inj_h.size());
+    for (size_t q = 0; q < S.inj_h.size(); ++q) i32[q] = InjectItem32{tr(S.inj_h[q].src), S.inj_h[q].c, 0.0};
+    upload(S.d_jobs32, j32.data(), j32.size(), ctx->stream);
+    upload(S.d_inj32, i32.data(), i32.size(), ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));   // j32 / i32 are released at the end of this block
+    S.lid32 = ctx->s32.Lid;
+    S.rid32 = ctx->s32.Rid;
+  }
   S.dims = dims;
   S.dc = dc;
   S.lid = Lid;
@@ -800,7 +841,10 @@ static void run_sweep_adjoint(mps_plan* p, const std::vector<int>& dims, const m
   // precision 1 computed the energy on FP32 environments: the adjoint takes
   // the FP64 ones of the same state
   if (st->trunc.precision == 1) run_identity_envs(const_cast<mps_state*>(st));
-  if (!S.built || S.dims != dims || S.lid != ctx->sb.Lid || S.rid != ctx->sb.Rid) build_sweep_adjoint(p, S, dims);
+  const bool f32 = st->trunc.precision == 1;
+  if (!S.built || S.dims != dims || S.lid != ctx->sb.Lid || S.rid != ctx->sb.Rid || S.f32 != f32 ||
+      (f32 && (S.lid32 != ctx->s32.Lid || S.rid32 != ctx->s32.Rid)))
+    build_sweep_adjoint(p, S, dims);
   const int N = p->N, dc = S.dc;
   const size_t dd = (size_t)dc * dc;
   zd* Lagg = (zd*)S.Lagg.p;
@@ -812,7 +856,30 @@ static void run_sweep_adjoint(mps_plan* p, const std::vector<int>& dims, const m
   HIPCHK(hipMemsetAsync(Ragg, 0, (size_t)(N + 1) * dd * sizeof(zd), s));
   const EnvJob* J = (const EnvJob*)S.d_jobs.p;
   const InjectItem* I = (const InjectItem*)S.d_inj.p;
+  const EnvJob32* J32 = (const EnvJob32*)S.d_jobs32.p;
+  const InjectItem32* I32 = (const InjectItem32*)S.d_inj32.p;
+  const cf* B32 = ctx->s32.B;   // the FP32 sites of st (converted by its energy sweep)
   for (auto& ch : S.chunks) {
+    if (f32) {
+      // the per-term transfers on the matrix cores; cotangents accumulate in FP64
+      for (int m = ch.hi; m >= ch.lo; --m) {
+        const auto& sj = ch.right[m - ch.lo];
+        if (sj.nj) HIPCHK(launch_env32_right(J32 + sj.off, sj.nj, B32 + (size_t)m * site, dims[m], dims[m + 1], dc, s));
+      }
+      for (int m = ch.lo; m <= ch.hi; ++m) {
+        const auto& ij = ch.injR[m - ch.lo];
+        if (ij.nj) HIPCHK(launch_inject32(I32 + ij.off, ij.nj, Ragg + (size_t)m * dd, dims[m], dc, s));
+      }
+      for (int n = ch.lo; n <= ch.hi; ++n) {
+        const auto& sj = ch.left[n - ch.lo];
+        if (sj.nj)
+          HIPCHK(launch_env32_left(J32 + sj.off, sj.nj, B32 + (size_t)n * site, Bbar + (size_t)n * site, dims[n],
+                                   dims[n + 1], dc, s));
+        const auto& ij = ch.injL[n - ch.lo];
+        if (ij.nj) HIPCHK(launch_inject32(I32 + ij.off, ij.nj, Lagg + (size_t)(n + 1) * dd, dims[n + 1], dc, s));
+      }
+      continue;
+    }
     for (int m = ch.hi; m >= ch.lo; --m) {
       const auto& sj = ch.right[m - ch.lo];
       const int a = dims[m], b = dims[m + 1];

@@ -206,6 +206,30 @@ hipError_t launch_finalize(const MpsView& st, SweepBuffers& sb, int n, const int
 hipError_t launch_energy_sum(const MpsView& st, SweepBuffers& sb, const double* coeff, int64_t K, double c0,
                              hipStream_t stream);
 
+// One environment-transfer job of the sweep adjoint with FP32 buffers
+// (precision 1): the FP64 job's fields with its pointers moved to the FP32
+// copies of the same buffers.
+struct EnvJob32 {
+  const cf* in;   // input environment
+  cf* out;        // output environment
+  cf* y;          // stage-1 buffer ([dc][2 dc])
+  const cf* rr;   // right environment of the contribution
+  cf* g;          // contribution buffer ([dc][2 dc])
+  double c;       // term coefficient
+  int xb;         // bit flip of the site operator
+  int acc;        // stage 2 accumulates into out
+  zd o0, o1;      // O[i^x, i] = o_i
+};
+struct InjectItem32 {
+  const cf* src;
+  double c;
+  double pad;
+};
+hipError_t launch_env32_right(const EnvJob32* jobs, int nj, const cf* B, int a, int b, int dc, hipStream_t s);
+hipError_t launch_env32_left(const EnvJob32* jobs, int nj, const cf* B, zd* Bbar, int a, int b, int dc,
+                             hipStream_t s);
+hipError_t launch_inject32(const InjectItem32* items, int ni, zd* dst, int d, int dc, hipStream_t s);
+
 hipError_t launch_sites_f32(const MpsView& st, cf* B32, hipStream_t stream);
 hipError_t launch_identity_envs_f32(const MpsView& st, Sweep32& s, hipStream_t stream);
 hipError_t launch_transfer_f32(const MpsView& st, Sweep32& s, int n, const SweepJob* jobs, int njobs,

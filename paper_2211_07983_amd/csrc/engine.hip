@@ -256,13 +256,14 @@ void DevHamiltonian::upload_from(const mps_paulisum* h, int N, int dcap, hipStre
 
 void mps_ctx::ensure_sweep(int N, int dcap, int chunk, int precision) {
   const size_t dd = (size_t)dcap * dcap;
-  // the FP64 identity environments also serve the gradient and hold Z
+  // the FP64 identity environments (and their scratch Yid) also serve the
+  // gradient in either precision, and Lid holds Z
   sb.Lid = (zd*)b_Lid.ensure((N + 1) * dd * sizeof(zd));
   sb.Rid = (zd*)b_Rid.ensure((N + 1) * dd * sizeof(zd));
+  sb.Yid = (zd*)b_Yid.ensure(2 * dd * sizeof(zd));
   if (precision == 0) {
     sb.Lslots = (zd*)b_Lslots.ensure((size_t)chunk * dd * sizeof(zd));
     sb.Y = (zd*)b_Y.ensure((size_t)chunk * 2 * dd * sizeof(zd));
-    sb.Yid = (zd*)b_Yid.ensure(2 * dd * sizeof(zd));
   } else {
     s32.B = (cf*)b_B32.ensure((size_t)N * 2 * dd * sizeof(cf));
     s32.Lid = (cf*)b_Lid32.ensure((N + 1) * dd * sizeof(cf));

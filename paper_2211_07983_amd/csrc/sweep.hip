@@ -150,6 +150,7 @@ __global__ void k_set_unit_env(SweepBuffers sb, int dc, int site_left, int site_
 }
 
 hipError_t launch_identity_envs(const MpsView& st, SweepBuffers& sb, hipStream_t stream) {
+  if (!sb.Lid || !sb.Rid || !sb.Yid) return hipErrorInvalidValue;   // buffers not set up
   const int dc = st.dcap, N = st.N;
   hipLaunchKernelGGL(k_set_unit_env, dim3(1), dim3(64), 0, stream, sb, dc, 0, N);
   const int t1 = (dc + ZT_M - 1) / ZT_M, t2 = (2 * dc + ZT_N - 1) / ZT_N;
@@ -166,6 +167,7 @@ hipError_t launch_identity_envs(const MpsView& st, SweepBuffers& sb, hipStream_t
 
 hipError_t launch_transfer(const MpsView& st, SweepBuffers& sb, int n, const SweepJob* jobs, int njobs,
                            hipStream_t stream) {
+  if (!sb.Lid || !sb.Lslots || !sb.Y) return hipErrorInvalidValue;
   const int dc = st.dcap;
   const int t1 = (dc + ZT_M - 1) / ZT_M, t2 = (2 * dc + ZT_N - 1) / ZT_N;
   for (int z0 = 0; z0 < njobs; z0 += 65535) {

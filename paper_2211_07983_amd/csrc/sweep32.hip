@@ -274,6 +274,7 @@ hipError_t launch_sites_f32(const MpsView& st, cf* B32, hipStream_t stream) {
 }
 
 hipError_t launch_identity_envs_f32(const MpsView& st, Sweep32& s, hipStream_t stream) {
+  if (!s.B || !s.Lid || !s.Rid || !s.Yid) return hipErrorInvalidValue;   // buffers not set up
   const int dc = st.dcap, N = st.N;
   hipLaunchKernelGGL(k_unit_env_f32, dim3(1), dim3(64), 0, stream, s, dc, 0, N);
   const int t1 = (dc + CT_M - 1) / CT_M, t2 = (2 * dc + CT_N - 1) / CT_N;
@@ -290,6 +291,7 @@ hipError_t launch_identity_envs_f32(const MpsView& st, Sweep32& s, hipStream_t s
 
 hipError_t launch_transfer_f32(const MpsView& st, Sweep32& s, int n, const SweepJob* jobs, int njobs,
                                hipStream_t stream) {
+  if (!s.B || !s.Lid || !s.Lslots || !s.Y) return hipErrorInvalidValue;
   const int dc = st.dcap;
   const int t1 = (dc + CT_M - 1) / CT_M, t2 = (2 * dc + CT_N - 1) / CT_N;
   for (int z0 = 0; z0 < njobs; z0 += 65535) {
@@ -316,5 +318,168 @@ hipError_t launch_norm_from_f32(const MpsView& st, Sweep32& s, zd* dst, hipStrea
   Sweep32 at = s;
   at.Lid = s.Lid + (size_t)st.N * st.dcap * st.dcap;
   hipLaunchKernelGGL(k_norm_from_f32, dim3(1), dim3(64), 0, stream, at, dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sweep adjoint, precision 1: the per-term environment transfers of the
+// cotangent sweep on the matrix cores (the same GEMM shapes as the energy
+// sweep); contributions and injections accumulate into FP64 cotangents.
+// ---------------------------------------------------------------------------
+__device__ inline cf cf_of(zd z) { return cmk((float)z.x, (float)z.y); }
+
+// Y = in [B^0 | B^1] (a x 2b), column c = i b + beta
+__global__ __launch_bounds__(256) void k_env32_left1(const EnvJob32* jobs, const cf* B, int a, int b, int dc) {
+  const EnvJob32& jb = jobs[blockIdx.z];
+  const int i0 = blockIdx.y * CT_M, j0 = blockIdx.x * CT_N;
+  if (i0 >= a || j0 >= 2 * b) return;
+  const cf* in = jb.in;
+  cf* y = jb.y;
+  ctile_mfma<true, false>(
+      a, 2 * b, a, i0, j0, [&](int r, int k) { return in[(size_t)r * dc + k]; },
+      [&](int k, int c) {
+        const int i = c >= b, be = c - i * b;
+        return B[(size_t)k * 2 * dc + i * dc + be];
+      },
+      [&](int r, int c, cf v) {
+        const int i = c >= b, be = c - i * b;
+        y[(size_t)r * 2 * dc + i * dc + be] = v;
+      });
+}
+
+// out[b', b] (+)= sum_{i, a'} o_i conj(B^{i^x}[a', b']) Y[a', i, b]
+__global__ __launch_bounds__(256) void k_env32_left2(const EnvJob32* jobs, const cf* B, int a, int b, int dc) {
+  const EnvJob32& jb = jobs[blockIdx.z];
+  const int i0 = blockIdx.y * CT_M, j0 = blockIdx.x * CT_N;
+  if (i0 >= b || j0 >= b) return;
+  const cf o0 = cf_of(jb.o0), o1 = cf_of(jb.o1);
+  const int xb = jb.xb, acc = jb.acc;
+  const cf* y = jb.y;
+  cf* out = jb.out;
+  ctile_mfma<false, false>(
+      b, b, 2 * a, i0, j0,
+      [&](int r, int k) {
+        const int i = k >= a, al = k - i * a;
+        return cmul(i ? o1 : o0, cconj(B[(size_t)al * 2 * dc + (i ^ xb) * dc + r]));
+      },
+      [&](int k, int c) {
+        const int i = k >= a, al = k - i * a;
+        return y[(size_t)al * 2 * dc + i * dc + c];
+      },
+      [&](int r, int c, cf v) {
+        cf* o = out + (size_t)r * dc + c;
+        *o = acc ? cmk(o->x + v.x, o->y + v.y) : v;
+      });
+}
+
+// Yr[(i, a'), b] = sum_b' conj(B^{i^x}[a', b']) in[b', b]   (2a x b, ld dc)
+__global__ __launch_bounds__(256) void k_env32_right1(const EnvJob32* jobs, const cf* B, int a, int b, int dc) {
+  const EnvJob32& jb = jobs[blockIdx.z];
+  const int i0 = blockIdx.y * CT_M, j0 = blockIdx.x * CT_N;
+  if (i0 >= 2 * a || j0 >= b) return;
+  const int xb = jb.xb;
+  const cf* in = jb.in;
+  cf* y = jb.y;
+  ctile_mfma<true, false>(
+      2 * a, b, b, i0, j0,
+      [&](int r, int k) {
+        const int i = r >= a, al = r - i * a;
+        return cconj(B[(size_t)al * 2 * dc + (i ^ xb) * dc + k]);
+      },
+      [&](int k, int c) { return in[(size_t)k * dc + c]; },
+      [&](int r, int c, cf v) { y[(size_t)r * dc + c] = v; });
+}
+
+// out[a', a] (+)= sum_{i, b} o_i Yr[(i, a'), b] B^i[a, b]
+__global__ __launch_bounds__(256) void k_env32_right2(const EnvJob32* jobs, const cf* B, int a, int b, int dc) {
+  const EnvJob32& jb = jobs[blockIdx.z];
+  const int i0 = blockIdx.y * CT_M, j0 = blockIdx.x * CT_N;
+  if (i0 >= a || j0 >= a) return;
+  const cf o0 = cf_of(jb.o0), o1 = cf_of(jb.o1);
+  const int acc = jb.acc;
+  const cf* y = jb.y;
+  cf* out = jb.out;
+  ctile_mfma<true, true>(
+      a, a, 2 * b, i0, j0,
+      [&](int r, int k) {
+        const int i = k >= b, be = k - i * b;
+        return cmul(i ? o1 : o0, y[(size_t)(i * a + r) * dc + be]);
+      },
+      [&](int k, int c) {
+        const int i = k >= b, be = k - i * b;
+        return B[(size_t)c * 2 * dc + i * dc + be];
+      },
+      [&](int r, int c, cf v) {
+        cf* o = out + (size_t)r * dc + c;
+        *o = acc ? cmk(o->x + v.x, o->y + v.y) : v;
+      });
+}
+
+// g[a][i][b] = c conj(o_i) sum_b' Y[a][i^x][b'] rr[b][b']; blockIdx.y = i * tiles_a + row tile
+__global__ __launch_bounds__(256) void k_env32_contrib(const EnvJob32* jobs, int a, int b, int dc) {
+  const EnvJob32& jb = jobs[blockIdx.z];
+  const int tiles_a = (a + CT_M - 1) / CT_M;
+  const int i = blockIdx.y / tiles_a;
+  const int i0 = (blockIdx.y % tiles_a) * CT_M, j0 = blockIdx.x * CT_N;
+  if (i0 >= a || j0 >= b) return;
+  const int src = i ^ jb.xb;
+  const zd o = i ? jb.o1 : jb.o0;
+  const cf w = cmk((float)(jb.c * o.x), (float)(-jb.c * o.y));
+  const cf* y = jb.y;
+  const cf* rr = jb.rr;
+  cf* g = jb.g;
+  ctile_mfma<true, true>(
+      a, b, b, i0, j0, [&](int r, int k) { return y[(size_t)r * 2 * dc + src * dc + k]; },
+      [&](int k, int c) { return rr[(size_t)c * dc + k]; },
+      [&](int r, int c, cf v) { g[(size_t)r * 2 * dc + i * dc + c] = cmul(w, v); });
+}
+
+// Bbar_n[a][i][b] += sum_z g_z[a][i][b] in FP64 (fixed order)
+__global__ void k_env32_reduce(const EnvJob32* jobs, int nj, zd* Bbar, int a, int b, int dc) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a * 2 * b) return;
+  const int al = e / (2 * b), rem = e % (2 * b), i = rem / b, be = rem % b;
+  const size_t off = (size_t)al * 2 * dc + i * dc + be;
+  zd s = Bbar[off];
+  for (int z = 0; z < nj; ++z) {
+    const cf v = jobs[z].g[off];
+    s = zmk(s.x + (double)v.x, s.y + (double)v.y);
+  }
+  Bbar[off] = s;
+}
+
+// dst[r][c] += sum_z coeff_z src_z[r][c] for r, c < d, in FP64 (fixed order)
+__global__ void k_inject32(const InjectItem32* items, int ni, zd* dst, int d, int dc) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d * d) return;
+  const size_t off = (size_t)(e / d) * dc + (e % d);
+  zd s = dst[off];
+  for (int z = 0; z < ni; ++z) {
+    const cf v = items[z].src[off];
+    s = zmk(fma(items[z].c, (double)v.x, s.x), fma(items[z].c, (double)v.y, s.y));
+  }
+  dst[off] = s;
+}
+
+static inline dim3 grid64(int M, int N, int z) { return dim3((N + CT_N - 1) / CT_N, (M + CT_M - 1) / CT_M, z); }
+
+hipError_t launch_env32_right(const EnvJob32* jobs, int nj, const cf* B, int a, int b, int dc, hipStream_t s) {
+  hipLaunchKernelGGL(k_env32_right1, grid64(2 * a, b, nj), dim3(256), 0, s, jobs, B, a, b, dc);
+  hipLaunchKernelGGL(k_env32_right2, grid64(a, a, nj), dim3(256), 0, s, jobs, B, a, b, dc);
+  return hipGetLastError();
+}
+
+hipError_t launch_env32_left(const EnvJob32* jobs, int nj, const cf* B, zd* Bbar, int a, int b, int dc,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_env32_left1, grid64(a, 2 * b, nj), dim3(256), 0, s, jobs, B, a, b, dc);
+  const int ta = (a + CT_M - 1) / CT_M;
+  hipLaunchKernelGGL(k_env32_contrib, dim3((b + CT_N - 1) / CT_N, 2 * ta, nj), dim3(256), 0, s, jobs, a, b, dc);
+  hipLaunchKernelGGL(k_env32_reduce, dim3((a * 2 * b + 255) / 256), dim3(256), 0, s, jobs, nj, Bbar, a, b, dc);
+  hipLaunchKernelGGL(k_env32_left2, grid64(b, b, nj), dim3(256), 0, s, jobs, B, a, b, dc);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject32(const InjectItem32* items, int ni, zd* dst, int d, int dc, hipStream_t s) {
+  hipLaunchKernelGGL(k_inject32, dim3((d * d + 255) / 256), dim3(256), 0, s, items, ni, dst, d, dc);
   return hipGetLastError();
 }

@@ -73,20 +73,46 @@ def test_fp32_energy_against_oracle_and_fp64_path(ctx, name):
     assert rel(e64, gold["E"]) <= 1e-10
 
 
-def test_fp32_plan_energy_grad(ctx):
-    """A plan in precision 1: E from the FP32 sweep, the gradient from the FP64
-    adjoint sweep of the same state; both against the oracle."""
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_fp32_plan_energy_grad(ctx, name):
+    """A plan in precision 1: E from the FP32 sweep, the site cotangents from
+    the FP32 adjoint sweep (FP64 accumulation), the gate chain in FP64; E and
+    the gradient against the oracle, single and batched.  The gradient bound:
+    the cotangent of a site is a sum of term transfers with the same per-term
+    error as the energy's, so relative to the largest entry it is within
+    term_bound * sum_k |c_k| / max |g|; 1e-5 is above that for both sizes."""
     from paper_2211_07983_amd import Plan
-    p, g = configs.load("c1")
-    gold = golden()["c1"]
+    p, g = configs.load(name)
+    gold = golden()[name]
     plan = Plan(ctx, p.occ, g, p.n_qubits, p.ham_x, p.ham_z, p.ham_c, p.c0, p.bond_dim, p.eps, precision=1)
     e, grad, _ = plan.energy_grad(p.theta)
     ref = np.array(gold["grad"])
     gerr = np.abs(grad - ref).max() / np.abs(ref).max()
-    print(f"c1 fp32 plan: E error {abs(e - gold['E']):.2e} Ha, gradient error {gerr:.2e} (relative to max)")
+    print(f"{name} fp32 plan: E error {abs(e - gold['E']):.2e} Ha, gradient error {gerr:.2e} (relative to max)")
     assert abs(e - gold["E"]) <= term_bound(p) * np.abs(p.ham_c).sum()
     assert gerr <= 1e-5
+    eb, gb, _ = plan.energy_grad_batched(np.stack([p.theta, p.theta]))
+    assert abs(eb[1] - e) <= 1e-12 * abs(e)
+    assert np.abs(gb[1] - grad).max() <= 1e-9 * np.abs(grad).max()
     plan.free()
+
+
+def test_fp32_gradient_first_in_a_fresh_context():
+    """A context whose first and only work is a precision-1 gradient: every
+    buffer of the FP32 sweep and of the FP64 environments that the gradient
+    takes must be set up by that call itself (regression: the FP64 identity
+    scratch was only allocated by an FP64 energy sweep)."""
+    from paper_2211_07983_amd import Context, Plan
+    p, g = configs.load("c1")
+    gold = golden()["c1"]
+    c = Context(0)
+    plan = Plan(c, p.occ, g, p.n_qubits, p.ham_x, p.ham_z, p.ham_c, p.c0, p.bond_dim, p.eps, precision=1)
+    e, grad, _ = plan.energy_grad(p.theta)
+    ref = np.array(gold["grad"])
+    assert abs(e - gold["E"]) <= term_bound(p) * np.abs(p.ham_c).sum()
+    assert np.abs(grad - ref).max() <= 1e-5 * np.abs(ref).max()
+    plan.free()
+    c.close()
 
 
 def test_precision_validation(ctx):
