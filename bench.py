@@ -165,11 +165,11 @@ def cpu_baseline_sample(prob, gates, eps, budget_s=25.0):
 # prefix of the kernel source the counters were taken on: a changed source
 # reports null.
 TRAFFIC = {
-    ("evalgrad", "c2"): {"source": "paper_2211_07983_amd/csrc/gate.hip", "sha": "87f58631c2e081d2",
-                         "fetch_bytes": 132.75e9, "write_bytes": 169.49e9,
+    ("evalgrad", "c2"): {"source": "paper_2211_07983_amd/csrc/gate.hip", "sha": "816a029dcaada8c5",
+                         "fetch_bytes": 132.50e9, "write_bytes": 168.17e9,
                          "per": "forward launch of k_chain_lanes<16>, 64 lanes x 512 gates"},
-    ("sweep", "c3"): {"source": "paper_2211_07983_amd/csrc/sweep32.hip", "sha": "2b6a464e9cd741ba",
-                      "fetch_bytes": 276.68e9, "write_bytes": 106.78e9,
+    ("sweep", "c3"): {"source": "paper_2211_07983_amd/csrc/sweep32.hip", "sha": "9313886d959f9260",
+                      "fetch_bytes": 276.64e9, "write_bytes": 106.78e9,
                       "per": "one sweep (all k_left1_f32 + k_left2_f32 dispatches)"},
 }
 
