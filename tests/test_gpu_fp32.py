@@ -115,6 +115,22 @@ def test_fp32_gradient_first_in_a_fresh_context():
     c.close()
 
 
+def test_fp32_full_size_24_qubits(ctx):
+    """Full-size case of the matrix-core sweep: the 24-qubit, D = 128 state after
+    its first 3000 gates (middle bonds 128), all 29736 terms, against the FP64
+    path on the same circuit: every term value within the FP32 bound."""
+    from gpu_util import Prefix
+    p, g = configs.load("c3")
+    pre = Prefix(g, 3000)
+    e32, tv32, _ = fp32_energy(ctx, p, pre, p.theta)
+    e64, tv64, _, _, st = gpu_energy(ctx, p, pre, p.theta, terms=True)
+    st.free()
+    dt = np.abs(np.asarray(tv32) - np.asarray(tv64)).max()
+    print(f"c3 prefix fp32: E difference {abs(e32 - e64):.2e} Ha, max term diff {dt:.2e}")
+    assert dt <= term_bound(p)
+    assert abs(e32 - e64) <= 1e-6
+
+
 def test_precision_validation(ctx):
     from paper_2211_07983_amd import MPSError, State
     p, _ = configs.load("c1")

@@ -53,6 +53,30 @@ def test_paper_threshold_energy_grad_matches_oracle(ctx):
     plan.free()
 
 
+def test_benchmark_configuration_batched(ctx):
+    """The benchmark's own launch configuration: 14 qubits at eps = 1e-6,
+    512-gate checkpoints, as many vectors as one launch holds (the configured
+    theta and the benchmark's seeded perturbations).  Vector 0 against the
+    oracle at the same threshold; two others (the second and the last) against
+    the single-vector path."""
+    p, g = configs.load("c2", eps=configs.PAPER_EPS)
+    gold = golden()["c2_paper"]
+    plan = make_plan(ctx, p, g, ckpt_gates=512)
+    nb = plan.lanes_per_launch()
+    assert nb >= 2
+    rng = np.random.default_rng(2024)
+    thetas = np.stack([p.theta] + [p.theta + 0.05 * rng.normal(size=p.theta.shape) for _ in range(nb - 1)])
+    eb, gb, st = plan.energy_grad_batched(thetas)
+    assert st["n_gates_applied"] == nb * g.n_gates
+    assert rel(eb[0], gold["E"]) <= 1e-10
+    assert grad_ok(gb[0], np.array(gold["grad"]))
+    for b in (1, nb - 1):
+        e1, g1, _ = plan.energy_grad(thetas[b])
+        assert abs(eb[b] - e1) <= 1e-13 * abs(e1)
+        assert np.abs(gb[b] - g1).max() <= 1e-12 * np.abs(g1).max()
+    plan.free()
+
+
 @pytest.mark.parametrize("name,nb", [("c1", 5), ("c2", 3)])
 def test_batched_equals_single(ctx, name, nb):
     """mps_energy_grad_batched on nb parameter vectors (the configured one and
