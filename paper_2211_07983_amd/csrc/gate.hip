@@ -150,7 +150,7 @@ __device__ inline bool jacobi_rotation(double al, double be, double gr, double g
   const double d = be - al;
   const double qd = sqrt(fma(d, d, 4.0 * g2));
   const double h = (d >= 0.0 ? 2.0 : -2.0) / (fabs(d) + qd);
-  c = 1.0 / sqrt(fma(h * h, g2, 1.0));
+  c = rsqrt(fma(h * h, g2, 1.0));
   const double ch = c * h;
   p = zmk(ch * gr, -ch * gi);    // c h conj(gamma)
   q = zmk(ch * gr, ch * gi);     // c h gamma
