@@ -1150,6 +1150,7 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   lc.nparts = ((2 * dc + ZT_M - 1) / ZT_M) * ((2 * dc + ZT_M - 1) / ZT_M);
   lc.eps = gw.eps;
   lc.tol = gw.tol;
+  lc.sched = gw.sched;
   lc.ck_B = lc.ck_dims = lc.ck_lam = 0;   // no checkpoint copies in the recompute
   AdjWork W;
   adjwork_layout(gw.ncap, dc, &W, (char*)p->work.ensure(adjwork_layout(gw.ncap, dc, nullptr, nullptr)));
@@ -1353,6 +1354,7 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
   lc.nparts = ((2 * dc + ZT_M - 1) / ZT_M) * ((2 * dc + ZT_M - 1) / ZT_M);
   lc.eps = gw.eps;
   lc.tol = gw.tol;
+  lc.sched = gw.sched;
   lc.ck_B = ck_B;
   lc.ck_dims = ck_dims;
   lc.ck_lam = ck_lam;
@@ -1618,6 +1620,7 @@ void plan_energy_grad_psr(mps_plan* p, const double* theta, int n_theta, double*
   lc.nparts = ((2 * dc + ZT_M - 1) / ZT_M) * ((2 * dc + ZT_M - 1) / ZT_M);
   lc.eps = gw.eps;
   lc.tol = gw.tol;
+  lc.sched = gw.sched;
   lc.ck_B = lc.ck_dims = lc.ck_lam = 0;
   std::vector<double> E(nev);
   std::vector<GateLane> lh(nmax);

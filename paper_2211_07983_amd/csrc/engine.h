@@ -1,5 +1,6 @@
 // Internal declarations shared by the engine's translation units.
 #pragma once
+#include <vector>
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -43,6 +44,7 @@ struct GateWork {
   double* gdmeta; // [4]
   int* rotflag;   // [128]
   double* nrm_part; // [256] per-tile |A|^2 partial sums of k_contract
+  const unsigned char* sched;   // Jacobi block schedules (jacobi_schedule_table)
   GateStats* stats;
   int ldc, ldv, ncap;
   double eps, tol;
@@ -61,6 +63,7 @@ struct SvdArgs {
   int* gmeta;
   double* gdmeta;
   int* rotflag;
+  const unsigned char* sched;   // Jacobi block schedules (nullable: round robin only)
   unsigned long long* bar;  // work-group barrier counter (zeroed before the launch)
   double* lam_out;
   GateStats* stats;
@@ -133,6 +136,7 @@ struct GateLane {
 
 // Launch constants shared by all lanes.
 struct LaneConst {
+  const unsigned char* sched;   // Jacobi block schedules (jacobi_schedule_table)
   GateTable gt;
   TapeLayout L;
   int ldc, ldv, ncap, dmax, max_sweeps, nparts;
@@ -162,6 +166,10 @@ hipError_t launch_contract(const MpsView& st, const GateTable& gt, int g, const 
 hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stream, GateMode mode = GATE_TAPE);
 hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t stream, GateMode mode = GATE_TAPE);
 size_t svd_shared_bytes(int dcap, int ldc, int ldv, GateMode mode);
+// Block-pair schedules of one Jacobi sweep for P = 1, 2, 4, ..., 64 work-groups
+// ([P index][round][work-group][2] block ids, concatenated); empty if the
+// construction fails its own check.
+std::vector<unsigned char> jacobi_schedule_table();
 hipError_t svd_set_attributes(int dcap, size_t shm);
 
 // ----------------------------------------------------------------------------

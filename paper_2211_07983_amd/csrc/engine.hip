@@ -63,6 +63,13 @@ void mps_ctx::ensure_gate_work(int dcap, const mps_trunc& tr, int max_sweeps) {
   gw.gdmeta = (double*)b_gdmeta.ensure(16 * sizeof(double));
   gw.rotflag = (int*)b_rot.ensure(128 * sizeof(int) + 64);   // flags, then the SVD barrier counter
   gw.nrm_part = (double*)b_nrm.ensure(256 * sizeof(double));
+  if (!b_sched.p) {
+    const std::vector<unsigned char> tab = jacobi_schedule_table();
+    if (tab.empty()) fail(MPS_EDEVICE, "Jacobi block schedule failed its check");
+    upload(b_sched, tab.data(), tab.size(), stream);
+    HIPCHK(hipStreamSynchronize(stream));   // tab is released at the end of this block
+  }
+  gw.sched = (const unsigned char*)b_sched.p;
   gw.stats = (GateStats*)b_stats.ensure(sizeof(GateStats));
   gw.eps = tr.eps;
   gw.dmax = tr.d_max;

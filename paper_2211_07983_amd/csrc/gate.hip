@@ -9,6 +9,8 @@
 
 #include <algorithm>
 
+#include <vector>
+
 #include "engine.h"
 
 
@@ -103,6 +105,21 @@ __device__ inline void tourney(int P, int k, int p, int& q0, int& q1) {
   }
 }
 
+// Blocks of work-group p in round k of a sweep over 2P blocks: the
+// precomputed schedule when P is a power of two (consecutive rounds of a
+// work-group share a block), else the round robin above.
+__device__ inline void round_blocks(const unsigned char* sched, int P, int k, int p, int& q0, int& q1) {
+  if (sched && (P & (P - 1)) == 0 && P <= 64) {
+    size_t off = 0;
+    for (int q = 1; q < P; q <<= 1) off += (size_t)(2 * q - 1) * q * 2;
+    const unsigned char* e = sched + off + ((size_t)k * P + p) * 2;
+    q0 = e[0];
+    q1 = e[1];
+  } else {
+    tourney(P, k, p, q0, q1);
+  }
+}
+
 // Cross-lane sums over groups of TPP consecutive lanes.  Every step pairs
 // lanes symmetrically (l <-> l^1, l^2, the two halves of 8, of 16, of 32), so
 // all lanes of a group end with bitwise identical totals and therefore take
@@ -173,16 +190,19 @@ __device__ inline zd rot_y(const zd u, const zd v, double c, const zd q) { retur
 // work-groups through the device-coherent level after each round's barrier,
 // so the loads are latency-bound; more in flight means fewer round trips).
 constexpr int LB = 16;
+// Slots: columns [0, W) of the LDS pair hold block q0, [W, 2W) block q1;
+// only the slots in [s0, s1) (in columns) are moved.
 __device__ inline void load_blocks(zd* dst, int ldst, const zd* src, int lds, int rows, int ncol, int W, int q0,
-                                   int q1, bool identity) {
-  const int tot = 2 * W * rows;
+                                   int q1, bool identity, int s0 = 0, int s1 = -1) {
+  if (s1 < 0) s1 = 2 * W;
+  const int tot = (s1 - s0) * rows;
   for (int e0 = threadIdx.x; e0 < tot; e0 += LB * 256) {
     zd buf[LB];
 #pragma unroll
     for (int u = 0; u < LB; ++u) {
       const int e = e0 + u * 256;
       if (e < tot) {
-        const int c = e / rows, r = e - c * rows;
+        const int c = s0 + e / rows, r = e - (c - s0) * rows;
         const int gc = (c < W ? q0 : q1) * W + (c % W);
         buf[u] = identity ? zmk(r == gc ? 1.0 : 0.0, 0.0) : (gc < ncol ? src[(size_t)gc * lds + r] : zmk(0.0, 0.0));
       }
@@ -191,7 +211,7 @@ __device__ inline void load_blocks(zd* dst, int ldst, const zd* src, int lds, in
     for (int u = 0; u < LB; ++u) {
       const int e = e0 + u * 256;
       if (e < tot) {
-        const int c = e / rows, r = e - c * rows;
+        const int c = s0 + e / rows, r = e - (c - s0) * rows;
         dst[c * ldst + r] = buf[u];
       }
     }
@@ -199,9 +219,10 @@ __device__ inline void load_blocks(zd* dst, int ldst, const zd* src, int lds, in
 }
 
 __device__ inline void store_blocks(zd* dst, int ldd, const zd* src, int lsrc, int rows, int ncol, int W, int q0,
-                                    int q1) {
-  for (int e = threadIdx.x; e < 2 * W * rows; e += 256) {
-    const int c = e / rows, r = e - c * rows;
+                                    int q1, int s0 = 0, int s1 = -1) {
+  if (s1 < 0) s1 = 2 * W;
+  for (int e = threadIdx.x; e < (s1 - s0) * rows; e += 256) {
+    const int c = s0 + e / rows, r = e - (c - s0) * rows;
     const int gc = (c < W ? q0 : q1) * W + (c % W);
     if (gc < ncol) dst[(size_t)gc * ldd + r] = src[c * lsrc + r];
   }
@@ -292,12 +313,24 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
   int sweep = 0;
   for (; sweep < s.max_sweeps; ++sweep) {
     if (t == 0) sh_rot = 0;
+    int hold0 = -1, hold1 = -1;   // blocks resident in the two LDS slots
     for (int k = 0; k < 2 * P - 1; ++k) {
       int q0, q1;
-      tourney(P, k, p, q0, q1);
+      round_blocks(s.sched, P, k, p, q0, q1);
       if (p < P) {
-        load_blocks(Al, mpad, s.A, s.lda, M, ncol, W, q0, q1, false);
-        if (ACC) load_blocks(Vl, vpad, s.V, s.ldv, ncol, ncol, W, q0, q1, sweep == 0 && k == 0);
+        // a block this work-group already holds stays in its slot
+        if (q0 == hold1 || q1 == hold0) {
+          const int q = q0;
+          q0 = q1;
+          q1 = q;
+        }
+        const int s0 = q0 == hold0 ? W : 0, s1 = q1 == hold1 ? W : 2 * W;
+        if (s0 < s1) {
+          load_blocks(Al, mpad, s.A, s.lda, M, ncol, W, q0, q1, false, s0, s1);
+          if (ACC) load_blocks(Vl, vpad, s.V, s.ldv, ncol, ncol, W, q0, q1, sweep == 0 && k == 0, s0, s1);
+        }
+        hold0 = q0;
+        hold1 = q1;
         __syncthreads();
         bool rot = false;
         if (k == 0) {
@@ -399,8 +432,18 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
           __syncthreads();
         }
         if (rot && lt == 0) sh_rot = 1;
-        store_blocks(s.A, s.lda, Al, mpad, M, ncol, W, q0, q1);
-        if (ACC) store_blocks(s.V, s.ldv, Vl, vpad, ncol, ncol, W, q0, q1);
+        // blocks that leave this work-group after this round go back to
+        // global memory (all of them after the sweep's last round)
+        int n0 = -1, n1 = -1;
+        if (k + 1 < 2 * P - 1) round_blocks(s.sched, P, k + 1, p, n0, n1);
+        const bool keep0 = hold0 == n0 || hold0 == n1, keep1 = hold1 == n0 || hold1 == n1;
+        const int t0 = keep0 ? W : 0, t1 = keep1 ? W : 2 * W;
+        if (t0 < t1) {
+          store_blocks(s.A, s.lda, Al, mpad, M, ncol, W, q0, q1, t0, t1);
+          if (ACC) store_blocks(s.V, s.ldv, Vl, vpad, ncol, ncol, W, q0, q1, t0, t1);
+        }
+        if (!keep0) hold0 = -1;
+        if (!keep1) hold1 = -1;
       }
       // Sweep finished with this round: count the work-groups that rotated.
       // The counter of this sweep (zeroed before the launch) is incremented
@@ -635,6 +678,7 @@ __device__ inline SvdArgs lane_svd_args(const GateLane& ln, const LaneConst& c, 
   s.gdmeta = R.dmeta;
   s.rotflag = ln.rotflag;
   s.bar = ln.bar;
+  s.sched = c.sched;
   s.lam_out = ln.st.lam + (size_t)(n + 1) * ln.st.dcap;
   s.stats = ln.stats;
   s.eps = c.eps;
@@ -808,6 +852,7 @@ static SvdArgs svd_args(const MpsView& st, int bond, GateWork& w, GateMode mode)
   s.gdmeta = w.gdmeta;
   s.rotflag = w.rotflag;
   s.bar = (unsigned long long*)(w.rotflag + 128);
+  s.sched = w.sched;
   s.lam_out = st.lam + (size_t)(bond + 1) * st.dcap;
   s.stats = w.stats;
   s.eps = w.eps;
@@ -827,6 +872,67 @@ hipError_t launch_contract(const MpsView& st, const GateTable& gt, int g, const 
   hipLaunchKernelGGL(k_contract, dim3(tiles, tiles), dim3(256), 0, stream, st, gt, g, theta, w.C, w.A, w.ldc,
                      w.nrm_part, mode == GATE_FWD ? 1 : 0, w.rotflag);
   return hipGetLastError();
+}
+
+// One sweep over 2P blocks (P a power of two) by P work-groups in 2P - 1
+// rounds, built so that a work-group keeps one of its two blocks from each
+// round to the next: the first P blocks T stay while the other P blocks S
+// pass along a ring (P rounds pair every T with every S); then the T blocks
+// among themselves and the S blocks among themselves, each the same problem
+// for P/2 work-groups, with S reordered so that every work-group again keeps
+// one block at the switch.
+static void schedule_rounds(int P, const std::vector<int>& L, std::vector<std::vector<std::pair<int, int>>>& out) {
+  out.clear();
+  if (P == 1) {
+    out.push_back({{L[0], L[1]}});
+    return;
+  }
+  for (int j = 0; j < P; ++j) {
+    std::vector<std::pair<int, int>> rd;
+    for (int i = 0; i < P; ++i) rd.push_back({L[i], L[P + (i + j) % P]});
+    out.push_back(rd);
+  }
+  const int h = P / 2;
+  std::vector<int> T(L.begin(), L.begin() + P), S2(P);
+  for (int i = 0; i < h; ++i) {
+    S2[i] = L[P + (h + i - 1 + P) % P];
+    S2[h + i] = L[P + (i - 1 + P) % P];
+  }
+  std::vector<std::vector<std::pair<int, int>>> a, b;
+  schedule_rounds(h, T, a);
+  schedule_rounds(h, S2, b);
+  for (int r = 0; r < P - 1; ++r) {
+    std::vector<std::pair<int, int>> rd = a[r];
+    rd.insert(rd.end(), b[r].begin(), b[r].end());
+    out.push_back(rd);
+  }
+}
+
+std::vector<unsigned char> jacobi_schedule_table() {
+  std::vector<unsigned char> tab;
+  for (int P = 1; P <= 64; P <<= 1) {
+    std::vector<int> L(2 * P);
+    for (int i = 0; i < 2 * P; ++i) L[i] = i;
+    std::vector<std::vector<std::pair<int, int>>> rounds;
+    schedule_rounds(P, L, rounds);
+    // check: 2P - 1 perfect matchings that meet every block pair once
+    if ((int)rounds.size() != 2 * P - 1) return {};
+    std::vector<char> met((size_t)4 * P * P, 0);
+    for (const auto& rd : rounds) {
+      if ((int)rd.size() != P) return {};
+      std::vector<char> used(2 * P, 0);
+      for (const auto& e : rd) {
+        if (e.first == e.second || used[e.first] || used[e.second]) return {};
+        used[e.first] = used[e.second] = 1;
+        char& m = met[(size_t)std::min(e.first, e.second) * 2 * P + std::max(e.first, e.second)];
+        if (m) return {};
+        m = 1;
+        tab.push_back((unsigned char)e.first);
+        tab.push_back((unsigned char)e.second);
+      }
+    }
+  }
+  return tab;
 }
 
 size_t svd_shared_bytes(int dcap, int ldc, int ldv, GateMode mode) {

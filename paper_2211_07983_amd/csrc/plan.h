@@ -71,6 +71,7 @@ struct mps_ctx {
   GateWork gw{};
   SweepBuffers sb{};
   DevBuf b_C, b_A, b_V, b_sv, b_perm, b_gmeta, b_gdmeta, b_rot, b_nrm, b_stats, b_stats2, b_theta;
+  DevBuf b_sched;   // Jacobi block schedules
   DevBuf b_Lid, b_Rid, b_Lslots, b_Y, b_Yid, b_energy, b_termval;
   DevBuf b_B32, b_Lid32, b_Rid32, b_Lslots32, b_Y32, b_Yid32;   // precision 1 sweep
   Sweep32 s32{};
