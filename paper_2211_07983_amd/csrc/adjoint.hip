@@ -1124,8 +1124,9 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   GateWork gw = ctx->gw;
   const TapeLayout L = tape_layout(dc, gw.ncap, gw.ldc, gw.ldv);
   const int K = p->opts.ckpt_gates;
-  // Segments are recomputed nl at a time (lanes), all lanes advancing one gate
-  // per launch; the adjoint then walks the batch's segments in reverse order.
+  // Segments are recomputed nl at a time, each segment a lane of one
+  // gate-chain launch; the adjoint then walks the batch's segments in reverse
+  // order.
   const size_t seg_bytes = (size_t)K * L.rec;
   const size_t tape_budget = (size_t)64 << 30;
   int nlanes = std::min({p->n_seg, lanes_max(dc), 64, (int)std::max<size_t>(1, tape_budget / seg_bytes)});

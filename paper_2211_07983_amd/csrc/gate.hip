@@ -5,10 +5,11 @@
 //   C~ = U s W  truncated to r values (one-sided Jacobi SVD, k_svd_jacobi)
 //   B~_n = C W_r^dagger / nu, B~_{n+1} = W_r, lambda_n = s_r / nu   (k_update_*)
 // All sizes are read from the device-side bond dimensions, so a whole circuit
-// is enqueued without any host synchronisation.
+// is enqueued without any host synchronisation.  k_chain_lanes runs the same
+// three steps for a run of gates of many independent MPS ("lanes") in one
+// cooperative launch.
 
 #include <algorithm>
-
 #include <vector>
 
 #include "engine.h"
@@ -86,8 +87,9 @@ __global__ __launch_bounds__(256) void k_contract(MpsView st, GateTable gt, int 
 // ----------------------------------------------------------------------------
 // One-sided block Jacobi SVD of A (M x ncol, column-major), accumulating the
 // right rotations in V (ncol x ncol).  P work-groups each hold a pair of
-// column blocks of width W in LDS; the pairs follow a round-robin tournament,
-// with a grid barrier between rounds.  Round 0 of a sweep orthogonalises all
+// column blocks of width W in LDS; the pairs follow a tournament over the 2P
+// blocks (round_blocks), with a barrier over the P work-groups between
+// rounds.  Round 0 of a sweep orthogonalises all
 // pairs inside both blocks, later rounds the cross pairs only, so a sweep
 // visits every column pair exactly once.  A rotation is skipped when
 // |a_i^H a_j| <= tol sqrt(|a_i|^2 |a_j|^2); the sweep loop stops after a sweep
