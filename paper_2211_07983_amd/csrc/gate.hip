@@ -701,7 +701,13 @@ __device__ inline void copy_words(unsigned long long* dst, const unsigned long l
 
 template <int W>
 __global__ __launch_bounds__(256) void k_chain_lanes(const GateLane* lanes, LaneConst c, int nblk, int record) {
-  const int lane = blockIdx.x / nblk, p = blockIdx.x % nblk;
+  // Work-groups are dispatched to the 8 XCDs round-robin (work-group i on XCD
+  // i % 8).  When the launch divides evenly, the nblk work-groups of a lane
+  // are taken from one XCD, so its barrier and block exchange stay there.
+  const int T = gridDim.x;
+  int slot = blockIdx.x;
+  if (T % 8 == 0 && (T / 8) % nblk == 0) slot = (blockIdx.x % 8) * (T / 8) + blockIdx.x / 8;
+  const int lane = slot / nblk, p = slot % nblk;
   const GateLane& ln = lanes[lane];
   extern __shared__ zd lds[];
   zd* sbuf = lds;    // tile-GEMM staging; the Jacobi blocks use the same LDS in between barriers
