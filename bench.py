@@ -165,8 +165,8 @@ def cpu_baseline_sample(prob, gates, eps, budget_s=25.0):
 # prefix of the kernel source the counters were taken on: a changed source
 # reports null.
 TRAFFIC = {
-    ("evalgrad", "c2"): {"source": "paper_2211_07983_amd/csrc/gate.hip", "sha": "c62ae5435bb9b666",
-                         "fetch_bytes": 112.40e9, "write_bytes": 116.73e9,
+    ("evalgrad", "c2"): {"source": "paper_2211_07983_amd/csrc/gate.hip", "sha": "4788d0911442c081",
+                         "fetch_bytes": 2.58e9, "write_bytes": 116.48e9,
                          "per": "forward launch of k_chain_lanes<16>, 64 lanes x 512 gates"},
     ("sweep", "c3"): {"source": "paper_2211_07983_amd/csrc/sweep32.hip", "sha": "9313886d959f9260",
                       "fetch_bytes": 276.64e9, "write_bytes": 106.78e9,
