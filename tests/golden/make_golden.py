@@ -67,8 +67,35 @@ def c3_prefix():
     return dict(gates=C3_PREFIX, E=e, Eim=eim, Z=Z.real, bonds=m.bond_dims(), lam_mid=m.lam[12].tolist())
 
 
+C5_PREFIX = 3000
+
+
+def c5_prefix():
+    """The first C5_PREFIX gates of the 40-qubit, D=256 workload (233000 terms):
+    energy and bonds at the parity threshold."""
+    p, g = configs.load("c5")
+    m = mps.forward(p, g, p.theta, count=C5_PREFIX)
+    e, eim, Z, _ = m.energy(p.ham_x, p.ham_z, p.ham_c, p.c0)
+    return dict(gates=C5_PREFIX, E=e, Eim=eim, Z=Z.real, bonds=m.bond_dims())
+
+
+def batched_instance(i):
+    """Instance i of the batched set (qubits and D drawn per instance): the
+    energy, gradient and bonds at its own D and the parity threshold."""
+    from vqe_inputs.compile import compile_problem
+    from vqe_inputs.problem import make_problem
+    n, ne, D, s1, s2 = configs.batched_instances()[i]
+    p = make_problem(f"c4_{i}", n, ne, D, configs.PARITY_EPS, s1, s2, 0.05)
+    g = compile_problem(p)
+    E, grad, info = mps.energy_grad(p, g, p.theta)
+    _, finfo = mps.energy(p, g, p.theta)
+    return dict(n_qubits=n, D=D, E=E, grad=grad.tolist(), bonds=finfo["bonds"],
+                discarded_sum=float(sum(finfo["discarded"])))
+
+
 ENTRIES = {"c1": lambda: exact_config("c1"), "c2": lambda: exact_config("c2"), "c2_paper": c2_paper,
-           "c3_prefix": c3_prefix, "c3_prefix_grad": c3_prefix_grad}
+           "c3_prefix": c3_prefix, "c3_prefix_grad": c3_prefix_grad, "c5_prefix": c5_prefix,
+           "c4_3": lambda: batched_instance(3), "c4_4": lambda: batched_instance(4)}
 
 
 def main(names):
