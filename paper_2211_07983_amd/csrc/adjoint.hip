@@ -1371,18 +1371,21 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   }
   for (int sg = 0; sg < n_seg; ++sg) {
+    // the last segment records its tape here, so the reverse pass starts
+    // without recomputing it
+    const bool last = sg == n_seg - 1;
     for (int l = 0; l < nl; ++l) {
       GateLane& ln = lh[l];
       ln.st = view_of(B.lanes[l]->st);
       ln.g0 = sg * K;
       ln.ng = std::min(G, (sg + 1) * K) - sg * K;
-      ln.rec_stride = 0;
+      ln.rec_stride = last ? 1 : 0;
       ln.tape = tape + (size_t)l * K * L.rec;
       ln.ckpt = (char*)B.lanes[l]->ckpt.p + (size_t)sg * ckpt_stride;
     }
     HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
     if (prof) HIPCHK(hipEventRecord(ev[0], s));
-    HIPCHK(launch_chain_lanes(lanes_d, nl, lc, false, lane_bars, s));
+    HIPCHK(launch_chain_lanes(lanes_d, nl, lc, last, lane_bars, s));
     if (prof) HIPCHK(hipEventRecord(ev[1], s));
     // the lane table is rewritten for the next segment only after this one
     // has been consumed
@@ -1424,13 +1427,16 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
   std::vector<GateDims> mx;
   for (int sg = n_seg - 1; sg >= 0; --sg) {
     const int g0 = sg * K, ng = std::min(G, (sg + 1) * K) - g0;
+    const bool taped = sg == n_seg - 1;   // recorded by the forward pass
     for (int l = 0; l < nl; ++l) {
       BatchLane* bl = B.lanes[l];
-      const char* base = (const char*)bl->ckpt.p + (size_t)sg * ckpt_stride;
       mps_state* rp = bl->rp;
-      HIPCHK(hipMemcpyAsync(rp->B.p, base, ck_B, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(rp->dims.p, base + ck_B, ck_dims, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(rp->lam.p, base + ck_lamoff, ck_lam, hipMemcpyDeviceToDevice, s));
+      if (!taped) {
+        const char* base = (const char*)bl->ckpt.p + (size_t)sg * ckpt_stride;
+        HIPCHK(hipMemcpyAsync(rp->B.p, base, ck_B, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(rp->dims.p, base + ck_B, ck_dims, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(rp->lam.p, base + ck_lamoff, ck_lam, hipMemcpyDeviceToDevice, s));
+      }
       GateLane& ln = lh[l];
       ln.st = view_of(rp);
       ln.g0 = g0;
@@ -1439,7 +1445,7 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
       ln.ckpt = nullptr;
     }
     HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
-    HIPCHK(launch_chain_lanes(lanes_d, nl, lc, true, lane_bars, s));
+    if (!taped) HIPCHK(launch_chain_lanes(lanes_d, nl, lc, true, lane_bars, s));
     read_lane_meta(lanes_d, lh, nl, L, K, dc, B.meta_dev, meta, dmeta, s);
     int err = 0;
     HIPCHK(hipMemcpyAsync(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost, s));
