@@ -338,6 +338,59 @@ def vqe_phase(args):
     print(json.dumps(line), flush=True)
 
 
+def instances_phase(args):
+    """The batched-instance set, one size class: the instances with
+    args.class_qubits qubits and D = args.class_d (one compiled circuit, a
+    seeded Hamiltonian and theta each) evaluated as lanes of shared gate-chain
+    launches (mps_energy_grad_multi), against the same instances evaluated one
+    after another on the plain FP64 path."""
+    import numpy as np
+    from vqe_inputs import configs
+    from vqe_inputs.compile import compile_problem
+    from vqe_inputs.problem import make_problem
+    from paper_2211_07983_amd import Context, Plan, energy_grad_multi
+    members = [i for i, (n, ne, D, s1, s2) in enumerate(configs.batched_instances())
+               if n == args.class_qubits and D == args.class_d]
+    if not members:
+        raise SystemExit(f"no instance with {args.class_qubits} qubits and D={args.class_d}")
+    ctx = Context(0)
+    probs, plans = [], []
+    for i in members:
+        n, ne, D, s1, s2 = configs.batched_instances()[i]
+        p = make_problem(f"c4_{i}", n, ne, D, args.eps, s1, s2, 0.05)
+        g = compile_problem(p)
+        probs.append(p)
+        plans.append(Plan(ctx, p.occ, g, p.n_qubits, p.ham_x, p.ham_z, p.ham_c, p.c0, p.bond_dim, p.eps,
+                          ckpt_gates=args.ckpt_gates))
+    thetas = np.stack([p.theta for p in probs])
+    log(f"class {args.class_qubits} q, D={args.class_d}: instances {members}, {g.n_gates} gates each")
+    t0 = time.perf_counter()
+    e_m, g_m, st = energy_grad_multi(plans, thetas)
+    t_multi = time.perf_counter() - t0
+    log(f"one call: {len(plans)} instances in {t_multi:.2f}s")
+    t0 = time.perf_counter()
+    worst = 0.0
+    for k, (pl, p) in enumerate(zip(plans, probs)):
+        e1, g1, _ = pl.energy_grad(p.theta)
+        worst = max(worst, abs(e1 - e_m[k]) / abs(e1), float(np.abs(g1 - g_m[k]).max() / np.abs(g1).max()))
+    t_seq = time.perf_counter() - t0
+    log(f"one after another: {t_seq:.2f}s; max relative difference {worst:.1e}")
+    line = {
+        "metric": "instance energy+grad evals/s, one size class of the batched-instance set in shared launches",
+        "value": len(plans) / t_multi, "unit": "instance-evals/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * t_multi, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded per-instance integrals and theta)",
+        "config": {"workload": f"batched-instance set, class {args.class_qubits} qubits D={args.class_d}: "
+                               f"{len(plans)} instances, {g.n_gates} NN gates, n_theta={probs[0].n_theta}, "
+                               f"eps={args.eps:g}",
+                   "instances": members, "sequential_evals_per_s": len(plans) / t_seq,
+                   "speedup_vs_sequential": t_seq / t_multi, "max_rel_diff_vs_single": worst,
+                   "max_bond": st["max_bond"]},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,7 +403,9 @@ def main():
     ap.add_argument("--ckpt-gates", type=int, default=512)
     ap.add_argument("--profile-every", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr", "vqe"], default="evalgrad")
+    ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr", "vqe", "instances"], default="evalgrad")
+    ap.add_argument("--class-qubits", type=int, default=12, help="--phase instances: qubit count of the class")
+    ap.add_argument("--class-d", type=int, default=64, help="--phase instances: bond dimension of the class")
     ap.add_argument("--vqe-iters", type=int, default=100, help="--phase vqe: iteration limit")
     ap.add_argument("--precision", type=int, choices=[0, 1], default=0,
                     help="evalgrad phase: 0 plain FP64, 1 Pauli sweeps and sweep adjoint on FP32 matrix cores")
@@ -375,6 +430,9 @@ def main():
         return
     if args.phase == "vqe":
         vqe_phase(args)
+        return
+    if args.phase == "instances":
+        instances_phase(args)
         return
     import numpy as np
     from vqe_inputs import configs

@@ -200,6 +200,24 @@ mps_status mps_energy_grad_batched(mps_plan* plan, int32_t n_batch, const double
                                    int32_t theta_on_device, double* energies, double* grads,
                                    mps_stats* stats);
 
+/* Energies and gradients of several problem instances that share one
+ * circuit, each with its own Hamiltonian (the batched-instance workload:
+ * independent instances of one size class, i.e. the same qubit count and
+ * bond dimension; Sec. 5 runs many molecules through one ansatz family).
+ * plans[n_plans]: created by mps_plan_create on one context from the same
+ * circuit (checked by a hash of the gate table), the same qubit count, d_max,
+ * eps, precision and gradient options; the Hamiltonians and occupation bits may
+ * differ.  Every instance is one lane of the same gate-chain launches
+ * (mps_plan_batch_width(plans[0]) lanes per launch, larger sets in groups),
+ * then each lane's energy and sweep adjoint run with its own plan.
+ * thetas: host [n_plans][n_theta]; energies: host [n_plans]; grads: host
+ * [n_plans][n_theta].  Results equal each plan's mps_energy_grad at its theta.
+ * stats (nullable): sums and maxima over the instances.  Incompatible plans,
+ * NULL or non-finite arguments: MPS_EINVAL before any work; the other errors as
+ * mps_energy_grad.  Every plan's working buffers may be overwritten.        */
+mps_status mps_energy_grad_multi(mps_plan* const* plans, int32_t n_plans, const double* thetas, int32_t n_theta,
+                                 double* energies, double* grads, mps_stats* stats);
+
 /* Parameter vectors that one batched launch holds for this plan (the SVD of
  * each vector occupies ceil(2 d_max / (2 W)) compute units); larger batches
  * run in groups of this size.  Returns <= 0 on error.                      */

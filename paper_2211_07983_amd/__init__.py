@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 from ._abi import GradOpts, PauliSum, Stats, Trunc
 
-__all__ = ["MPSError", "Context", "State", "Plan", "EnergyGrad", "lib"]
+__all__ = ["MPSError", "Context", "State", "Plan", "EnergyGrad", "energy_grad_multi", "lib"]
 
 
 def lib():
@@ -304,6 +304,28 @@ class Plan:
             self.free()
         except Exception:
             pass
+
+
+def energy_grad_multi(plans, thetas):
+    """Energies and gradients of several instances that share one circuit, each
+    plan with its own Hamiltonian, as lanes of the same gate-chain launches
+    (mps_energy_grad_multi).  plans: Plans of one context built from the same
+    circuit, truncation and options; thetas: [n_plans, n_theta].  Returns
+    (energies [n_plans], grads [n_plans, n_theta], stats)."""
+    plans = list(plans)
+    if not plans:
+        raise ValueError("no plans")
+    ctx = plans[0].ctx
+    th = np.ascontiguousarray(thetas, dtype=np.float64)
+    if th.ndim != 2 or th.shape[0] != len(plans):
+        raise ValueError("thetas must be [n_plans, n_theta]")
+    hs = (C.c_void_p * len(plans))(*[p.h for p in plans])
+    e = np.zeros(len(plans))
+    g = np.zeros_like(th)
+    s = Stats()
+    ctx.check(ctx._lib.mps_energy_grad_multi(hs, len(plans), th.ctypes.data_as(C.c_void_p), th.shape[1],
+                                             _ptr(e, C.c_double), g.ctypes.data_as(C.c_void_p), C.byref(s)))
+    return e, g, s.as_dict()
 
 
 def _energy_grad_function():

@@ -1293,8 +1293,12 @@ static BatchSet& batch_of(mps_plan* p) {
 }
 
 // One group of nl <= lanes_max lanes; thetas_dev holds nl consecutive vectors.
-static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double* energies, double* grads_dev,
-                          GateStats* gsum, double* prof_ms, int* prof_n) {
+// Lane l evaluates the energy of plan lp[l]: p itself for a batch of
+// parameter vectors, or plans that share p's circuit, truncation and options
+// but hold their own Hamiltonian and initial occupation (plans_compatible).
+// The lanes' buffers and the gate chain's constants come from p.
+static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double* thetas_dev, double* energies,
+                          double* grads_dev, GateStats* gsum, double* prof_ms, int* prof_n) {
   mps_ctx* ctx = p->ctx;
   hipStream_t s = ctx->stream;
   BatchSet& B = batch_of(p);
@@ -1362,7 +1366,7 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
   // ---- forward: all lanes through the circuit, one chain launch per
   // checkpoint segment (the launch copies each lane's state to its checkpoint
   // slot before the segment's first gate)
-  for (int l = 0; l < nl; ++l) init_product(B.lanes[l]->st, (const uint8_t*)p->state->occ.p);
+  for (int l = 0; l < nl; ++l) init_product(B.lanes[l]->st, (const uint8_t*)lp[l]->state->occ.p);
   // with profiling on, each chain launch is bracketed by events on the stream
   const bool prof = ctx->prof_every > 0;
   std::vector<hipEvent_t> ev;
@@ -1409,7 +1413,7 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
   std::vector<int> dims(N + 1);
   for (int l = 0; l < nl; ++l) {
     BatchLane* bl = B.lanes[l];
-    run_energy(bl->st, p->H);
+    run_energy(bl->st, lp[l]->H);
     double ev[3];
     HIPCHK(hipMemcpyAsync(ev, ctx->sb.energy, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(dims.data(), bl->st->dims.p, (N + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1418,7 +1422,7 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
     bl->Eim = ev[1];
     bl->Z = ev[2];
     energies[l] = ev[0];
-    run_sweep_adjoint(p, dims, bl->st, (zd*)bl->Bbar.p, bl->E, bl->Z);
+    run_sweep_adjoint(lp[l], dims, bl->st, (zd*)bl->Bbar.p, bl->E, bl->Z);
   }
   // ---- reverse pass, one segment of all lanes at a time
   std::vector<int> meta((size_t)nl * K * 16);
@@ -1511,28 +1515,12 @@ static void batched_group(mps_plan* p, int nl, const double* thetas_dev, double*
   }
 }
 
-void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_theta, int on_device,
-                              double* energies, double* grads, mps_stats* stats) {
-  mps_ctx* ctx = p->ctx;
-  hipStream_t s = ctx->stream;
-  if (nb < 1) fail(MPS_EINVAL, "n_batch must be >= 1");
-  if (n_theta != p->n_theta) fail(MPS_EINVAL, "n_theta does not match the circuit");
-  BatchSet& B = batch_of(p);
-  const int nth = std::max(1, n_theta);
-  double* th = (double*)B.thetas.ensure((size_t)nb * nth * sizeof(double));
-  if (n_theta > 0) {
-    std::vector<double> host((size_t)nb * n_theta);
-    if (on_device) {
-      HIPCHK(hipMemcpyAsync(host.data(), thetas, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-    } else {
-      std::memcpy(host.data(), thetas, host.size() * sizeof(double));
-    }
-    validate_theta(host.data(), (int)host.size());
-    HIPCHK(hipMemcpyAsync(th, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));   // host is released at the end of this block
-  }
-  double* gdev = (double*)p->grad.ensure((size_t)nb * nth * sizeof(double));
+// nb evaluations in groups of lanes_max lanes: evaluation b is plan lp[b] at
+// the vector th + b * nth (device); energies to the host, gradients to gdev.
+static void batched_run(mps_plan* p, mps_plan* const* lp, int nb, const double* th, double* energies,
+                        double* gdev, mps_stats* stats) {
+  hipStream_t s = p->ctx->stream;
+  const int nth = std::max(1, p->n_theta);
   const int per = lanes_max(p->state->dcap);
   GateStats gsum{};
   double prof_ms = 0.0;
@@ -1543,12 +1531,10 @@ void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_t
   HIPCHK(hipEventRecord(e0, s));
   for (int b0 = 0; b0 < nb; b0 += per) {
     const int nl = std::min(per, nb - b0);
-    batched_group(p, nl, th + (size_t)b0 * nth, energies + b0, gdev + (size_t)b0 * nth, &gsum, &prof_ms, &prof_n);
+    batched_group(p, lp + b0, nl, th + (size_t)b0 * nth, energies + b0, gdev + (size_t)b0 * nth, &gsum, &prof_ms,
+                  &prof_n);
   }
   HIPCHK(hipEventRecord(e1, s));
-  if (n_theta > 0)   // nth == n_theta here: rows are contiguous
-    HIPCHK(hipMemcpyAsync(grads, gdev, (size_t)nb * n_theta * sizeof(double),
-                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
@@ -1571,6 +1557,80 @@ void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_t
       stats->prof_svd_launches = prof_n;
     }
   }
+}
+
+void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_theta, int on_device,
+                              double* energies, double* grads, mps_stats* stats) {
+  mps_ctx* ctx = p->ctx;
+  hipStream_t s = ctx->stream;
+  if (nb < 1) fail(MPS_EINVAL, "n_batch must be >= 1");
+  if (n_theta != p->n_theta) fail(MPS_EINVAL, "n_theta does not match the circuit");
+  BatchSet& B = batch_of(p);
+  const int nth = std::max(1, n_theta);
+  double* th = (double*)B.thetas.ensure((size_t)nb * nth * sizeof(double));
+  if (n_theta > 0) {
+    std::vector<double> host((size_t)nb * n_theta);
+    if (on_device) {
+      HIPCHK(hipMemcpyAsync(host.data(), thetas, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    } else {
+      std::memcpy(host.data(), thetas, host.size() * sizeof(double));
+    }
+    validate_theta(host.data(), (int)host.size());
+    HIPCHK(hipMemcpyAsync(th, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // host is released at the end of this block
+  }
+  double* gdev = (double*)p->grad.ensure((size_t)nb * nth * sizeof(double));
+  const std::vector<mps_plan*> same(nb, p);
+  batched_run(p, same.data(), nb, th, energies, gdev, stats);
+  if (n_theta > 0)   // nth == n_theta here: rows are contiguous
+    HIPCHK(hipMemcpyAsync(grads, gdev, (size_t)nb * n_theta * sizeof(double),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// Plans whose evaluations can share gate-chain launches: one context, the
+// same circuit (gate tables equal by hash and size), qubit count, truncation,
+// capacity and reverse-pass options.  The Hamiltonian and the initial
+// occupation may differ.
+static void plans_compatible(mps_plan* const* plans, int n) {
+  const mps_plan* a = plans[0];
+  for (int i = 1; i < n; ++i) {
+    const mps_plan* b = plans[i];
+    if (!b) fail(MPS_EINVAL, "NULL plan");
+    if (b->ctx != a->ctx) fail(MPS_EINVAL, "plans belong to different contexts");
+    if (b->N != a->N || b->n_theta != a->n_theta) fail(MPS_EINVAL, "plans differ in qubit or parameter count");
+    if (b->C.G != a->C.G || b->C.hash != a->C.hash) fail(MPS_EINVAL, "plans hold different circuits");
+    if (b->trunc.d_max != a->trunc.d_max || b->trunc.eps != a->trunc.eps ||
+        b->trunc.precision != a->trunc.precision || b->state->dcap != a->state->dcap)
+      fail(MPS_EINVAL, "plans differ in truncation (d_max, eps or precision)");
+    if (b->opts.ckpt_gates != a->opts.ckpt_gates || b->opts.max_sweeps != a->opts.max_sweeps ||
+        b->opts.broaden != a->opts.broaden)
+      fail(MPS_EINVAL, "plans differ in gradient options");
+  }
+}
+
+void plan_energy_grad_multi(mps_plan* const* plans, int n, const double* thetas, int n_theta, double* energies,
+                            double* grads, mps_stats* stats) {
+  if (n < 1) fail(MPS_EINVAL, "n_plans must be >= 1");
+  mps_plan* p = plans[0];
+  if (!p) fail(MPS_EINVAL, "NULL plan");
+  plans_compatible(plans, n);
+  if (n_theta != p->n_theta) fail(MPS_EINVAL, "n_theta does not match the circuit");
+  hipStream_t s = p->ctx->stream;
+  BatchSet& B = batch_of(p);
+  const int nth = std::max(1, n_theta);
+  double* th = (double*)B.thetas.ensure((size_t)n * nth * sizeof(double));
+  if (n_theta > 0) {
+    validate_theta(thetas, n * n_theta);
+    HIPCHK(hipMemcpyAsync(th, thetas, (size_t)n * n_theta * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  double* gdev = (double*)p->grad.ensure((size_t)n * nth * sizeof(double));
+  batched_run(p, plans, n, th, energies, gdev, stats);
+  if (n_theta > 0)
+    HIPCHK(hipMemcpyAsync(grads, gdev, (size_t)n * n_theta * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
 }
 
 // ============================================================================

@@ -159,6 +159,23 @@ void DevCircuit::upload_from(const mps_circuit* c, hipStream_t s) {
   kind_h.assign(c->kind, c->kind + G);
   param_h = param;
   coeff_h = coeff;
+  // FNV-1a over everything the gate table holds, so that plans built from the
+  // same circuit can be recognised as such
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(&G, sizeof(G));
+  if (G > 0) {
+    mix(c->bond, (size_t)G * sizeof(int32_t));
+    mix(c->kind, (size_t)G * sizeof(int32_t));
+    mix(c->pre, (size_t)G * 32 * sizeof(double));
+    mix(post.data(), post.size() * sizeof(double));
+    mix(param.data(), param.size() * sizeof(int));
+    mix(coeff.data(), coeff.size() * sizeof(double));
+  }
+  hash = h;
   tab.bond = upload(d_bond, c->bond, G, s);
   tab.kind = upload(d_kind, c->kind, G, s);
   tab.pre = (const zd*)upload(d_pre, c->pre, (size_t)G * 32, s);

@@ -24,6 +24,7 @@ struct DevCircuit {
   GateTable tab{};
   std::vector<int> bond_h, kind_h, param_h;
   std::vector<double> coeff_h;
+  uint64_t hash = 0;   // of the uploaded gate table
   DevBuf d_bond, d_kind, d_pre, d_post, d_param, d_coeff;
   void upload_from(const mps_circuit* c, hipStream_t s);
 };

@@ -195,6 +195,14 @@ mps_status mps_energy_grad_batched(mps_plan* plan, int32_t n_batch, const double
   });
 }
 
+mps_status mps_energy_grad_multi(mps_plan* const* plans, int32_t n_plans, const double* thetas, int32_t n_theta,
+                                 double* energies, double* grads, mps_stats* stats) {
+  if (!plans || n_plans < 1 || !plans[0] || !energies || (n_theta > 0 && (!thetas || !grads))) return MPS_EINVAL;
+  return guarded(plans[0]->ctx, [&] {
+    plan_energy_grad_multi(plans, n_plans, thetas, n_theta, energies, grads, stats);
+  });
+}
+
 mps_status mps_energy_grad_psr(mps_plan* plan, const double* theta, int32_t n_theta, double* energy, double* grad,
                                double* gate_grad, mps_stats* stats) {
   if (!plan || !energy || (plan->n_theta > 0 && !grad)) return MPS_EINVAL;
