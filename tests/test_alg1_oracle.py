@@ -1,0 +1,109 @@
+"""Pins of the Algorithm 1 oracle (Sec. 4, memory-efficient back-propagation
+with Hamiltonian splitting) against what the mathematics fixes: the dense sum
+its compression must reproduce, the exact gradient of the exact sector
+simulator for every grouping when nothing is truncated (also at theta = 0,
+where the local gradient of the truncated evolution vanishes), and the
+reverse walk returning to the Hartree-Fock state.  In the truncating regime
+the result has no independent reference ("parity unpinned"); the test there
+only prints the relative error per D."""
+import numpy as np
+import pytest
+
+from oracle import alg1, mps
+from oracle import sector as sec
+from oracle import statevector as sv
+from vqe_inputs import configs
+
+
+def dense(m):
+    v = m.B[0].reshape(2, -1)
+    for n in range(1, m.N):
+        a, _, b = m.B[n].shape
+        v = (v @ m.B[n].reshape(a, 2 * b)).reshape(-1, b)
+    return v.reshape(-1)
+
+
+@pytest.fixture(scope="module")
+def six():
+    p, g = configs.small(6, 2, 8, seed=1)      # 6 qubits: D = 8 never truncates
+    return p, g, sec.UCCSD(p)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_compression_reproduces_the_dense_sum(six):
+    p, g, _ = six
+    psi = mps.forward(p, g, p.theta)
+    ks = [3, 10, 11, 40, 77]
+    terms = [(p.ham_c[k], alg1.pauli_apply(psi, p.ham_x[k], p.ham_z[k])) for k in ks]
+    phi, eta = alg1.compress(terms, D=64, eps=1e-14)
+    ap = sv.PauliApplier(p.n_qubits)
+    v = dense(psi)
+    ref = sum(p.ham_c[k] * ap.apply(v, p.ham_x[k], p.ham_z[k]) for k in ks)
+    assert np.abs(eta * dense(phi) - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(eta - np.linalg.norm(ref)) <= 1e-12 * eta
+    # right-canonical sites and exact Schmidt values, as the gate update needs
+    for n in range(1, p.n_qubits):
+        B = phi.B[n]
+        a = B.shape[0]
+        M = B.reshape(a, -1)
+        assert np.abs(M @ M.conj().T - np.eye(a)).max() <= 1e-12
+        s = sv.schmidt_values(dense(phi), p.n_qubits, n - 1)
+        assert np.abs(s[:len(phi.lam[n])] - phi.lam[n]).max() <= 1e-12
+    # one string twice is the same state with twice the weight
+    one = alg1.pauli_apply(psi, p.ham_x[3], p.ham_z[3])
+    two, eta2 = alg1.compress([(1.0, one), (1.0, one)], D=8, eps=1e-14)
+    assert abs(eta2 - 2.0) <= 1e-12
+    assert abs(abs(np.vdot(dense(two), dense(one))) - 1.0) <= 1e-12
+
+
+@pytest.mark.parametrize("per_group", [1, 4, 117])
+def test_exact_gradient_for_every_grouping(six, per_group):
+    """Sec. 4: the split of H into groups never changes the gradient when
+    nothing is truncated; 117 strings in one group is m = 1."""
+    p, g, u = six
+    assert len(p.ham_c) == 117
+    grad, info = alg1.energy_grad(p, g, p.theta, per_group=per_group)
+    ref = u.gradient(p.theta)
+    assert rel(grad, ref) <= 1e-9
+    assert len(info["eta"]) == -(-117 // per_group)
+
+
+def test_exact_at_theta_zero_where_the_local_gradient_vanishes(six):
+    p, g, u = six
+    th = np.zeros(p.n_theta)
+    ref = u.gradient(th)
+    assert np.linalg.norm(ref) > 0.1
+    grad, _ = alg1.energy_grad(p, g, th, per_group=4)
+    assert rel(grad, ref) <= 1e-9
+    _, local, _ = mps.energy_grad(p, g, th)
+    assert np.abs(local).max() <= 1e-12
+
+
+def test_reverse_walk_returns_to_the_initial_state(six):
+    p, g, _ = six
+    _, info = alg1.gate_gradient(p, g, p.theta, [[0]])
+    hf = sv.basis_state(p.occ)
+    assert abs(abs(np.vdot(hf, dense(info["psi_start"]))) - 1.0) <= 1e-12
+
+
+def test_exact_gradient_on_8_qubits():
+    """The 8-qubit problem at its exact D = 16, 16 strings per group."""
+    p, g = configs.load("c1")
+    u = sec.UCCSD(p)
+    grad, _ = alg1.energy_grad(p, g, p.theta, per_group=16)
+    assert rel(grad, u.gradient(p.theta)) <= 1e-9
+
+
+def test_truncating_regime_is_reported(six, capsys):
+    p, g, u = six
+    ref = u.gradient(p.theta)
+    out = []
+    for D in (2, 4, 8):
+        grad, _ = alg1.energy_grad(p, g, p.theta, per_group=4, D=D, eps=1e-12)
+        out.append((D, rel(grad, ref)))
+    print("Algorithm 1, 6 q, N_h/m = 4: relative gradient error per D " +
+          ", ".join(f"D={D}: {r:.2e}" for D, r in out))
+    assert out[-1][1] <= 1e-9
