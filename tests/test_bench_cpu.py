@@ -11,3 +11,28 @@ def test_more_than_one_gpu_is_refused_with_a_message():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "single GPU" in r.stderr and r.stdout == ""
+
+
+def test_every_phase_is_offered():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0
+    for phase in ("evalgrad", "sweep", "psr", "vqe", "instances"):
+        assert phase in r.stdout
+
+
+def test_instance_classes_share_their_circuit():
+    """The batched-instance phase and mps_energy_grad_multi rely on every
+    instance of one qubit count compiling to the same gate list."""
+    import numpy as np
+    from vqe_inputs import configs
+    from vqe_inputs.compile import compile_problem
+    from vqe_inputs.problem import make_problem
+    members = [i for i, (n, ne, D, s1, s2) in enumerate(configs.batched_instances()) if n == 12][:3]
+    lists = []
+    for i in members:
+        n, ne, D, s1, s2 = configs.batched_instances()[i]
+        lists.append(compile_problem(make_problem(f"c4_{i}", n, ne, D, 1e-6, s1, s2, 0.05)))
+    for g in lists[1:]:
+        for k in ("bond", "kind", "pre", "post", "param", "coeff"):
+            assert np.array_equal(np.asarray(getattr(g, k)), np.asarray(getattr(lists[0], k)))
