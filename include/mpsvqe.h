@@ -200,6 +200,25 @@ mps_status mps_energy_grad_batched(mps_plan* plan, int32_t n_batch, const double
                                    int32_t theta_on_device, double* energies, double* grads,
                                    mps_stats* stats);
 
+/* Gradient by the paper's memory-efficient back-propagation (Sec. 4,
+ * Algorithm 1) with the Hamiltonian split into groups of strings_per_group
+ * Pauli strings; only strings_per_group = 1 (m = N_h groups) is supported, so
+ * each group state phi_k = 2 c_k P_k Psi_M is an exact MPS of Psi_M's bonds
+ * and needs no compression.  Per string the circuit is walked backwards with
+ * two states (Psi <- U^dagger Psi; dE/dphi_g += Re <phi|dU_g/dphi_g|Psi>;
+ * phi <- U^dagger phi), each step the forward gate update with the plan's
+ * truncation; Psi stays normalised and phi keeps its norm (each truncation
+ * scales it by the kept norm).  Without truncation the result is the exact
+ * gradient at every theta, including theta = 0 where mps_energy_grad's local
+ * gradient of the truncated evolution vanishes; with truncation it is the
+ * global approximation the paper uses.  Costs 2 N_h passes over the circuit.
+ * theta, grad: host [n_theta]; energy: E(theta); gate_grad (nullable): host
+ * [n_gates], dE/dphi_g for PARAM gates and 0 for FIXED ones; stats: the
+ * forward pass's.  strings_per_group != 1: MPS_EINVAL; other errors as
+ * mps_energy_grad.                                                          */
+mps_status mps_energy_grad_alg1(mps_plan* plan, const double* theta, int32_t n_theta, int32_t strings_per_group,
+                                double* energy, double* grad, double* gate_grad, mps_stats* stats);
+
 /* Energies and gradients of several problem instances that share one
  * circuit, each with its own Hamiltonian (the batched-instance workload:
  * independent instances of one size class, i.e. the same qubit count and

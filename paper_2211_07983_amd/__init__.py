@@ -292,6 +292,19 @@ class Plan:
                                                          C.byref(s)))
         return e.value, g[:len(th)], gg[:self.n_gates], s.as_dict()
 
+    def energy_grad_alg1(self, theta, strings_per_group=1):
+        """Gradient by the paper's Algorithm 1 with one Pauli string per group:
+        (E, grad [n_theta], dE/dphi per gate [n_gates], stats)."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        e = C.c_double()
+        g = np.zeros(max(1, len(th)))
+        gg = np.zeros(max(1, self.n_gates))
+        s = Stats()
+        self.ctx.check(self.ctx._lib.mps_energy_grad_alg1(self.h, _ptr(th, C.c_double) if len(th) else None,
+                                                          len(th), strings_per_group, C.byref(e),
+                                                          _ptr(g, C.c_double), _ptr(gg, C.c_double), C.byref(s)))
+        return e.value, g[:len(th)], gg[:self.n_gates], s.as_dict()
+
     def free(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             self.ctx._lib.mps_plan_free(self.h)

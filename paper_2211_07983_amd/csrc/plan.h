@@ -108,6 +108,9 @@ struct mps_plan {
   DevBuf adjl_dev;                 // adjoint lane records of the current batch
   DevBuf meta_dev;                 // gathered gate sizes of the current batch
   DevCircuit C;
+  DevCircuit Cinv;                 // the circuit's inverse (Algorithm 1's reverse walk)
+  bool cinv_built = false;
+  DevBuf alg1_work, alg1_op;       // overlap workspace and operator of the reverse walk
   DevHamiltonian H;
   DevBuf theta, grad, gphi;
   DevBuf ckpt;                     // [n_seg][B | dims | lam] snapshots

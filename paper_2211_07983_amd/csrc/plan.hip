@@ -203,6 +203,14 @@ mps_status mps_energy_grad_multi(mps_plan* const* plans, int32_t n_plans, const 
   });
 }
 
+mps_status mps_energy_grad_alg1(mps_plan* plan, const double* theta, int32_t n_theta, int32_t strings_per_group,
+                                double* energy, double* grad, double* gate_grad, mps_stats* stats) {
+  if (!plan || !energy || (plan->n_theta > 0 && !grad)) return MPS_EINVAL;
+  return guarded(plan->ctx, [&] {
+    plan_energy_grad_alg1(plan, theta, n_theta, strings_per_group, energy, grad, gate_grad, stats);
+  });
+}
+
 mps_status mps_energy_grad_psr(mps_plan* plan, const double* theta, int32_t n_theta, double* energy, double* grad,
                                double* gate_grad, mps_stats* stats) {
   if (!plan || !energy || (plan->n_theta > 0 && !grad)) return MPS_EINVAL;

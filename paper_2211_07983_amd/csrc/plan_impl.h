@@ -48,6 +48,8 @@ void plan_forward_energy(mps_plan* p, const double* theta, int n_theta, int on_d
 void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats);
 void plan_energy_grad_psr(mps_plan* p, const double* theta, int n_theta, double* energy, double* grad,
                           double* gate_grad, mps_stats* stats);
+void plan_energy_grad_alg1(mps_plan* p, const double* theta, int n_theta, int per_group, double* energy,
+                           double* grad, double* gate_grad, mps_stats* stats);
 void plan_energy_grad_multi(mps_plan* const* plans, int n, const double* thetas, int n_theta, double* energies,
                             double* grads, mps_stats* stats);
 void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_theta, int on_device,

@@ -12,7 +12,7 @@ LIB = os.path.join(ROOT, "paper_2211_07983_amd", "libmpsvqe.so")
 
 def declared():
     text = open(HEADER).read()
-    decl = r"^\s*(?:mps_status|void|const char\s*\*|int64_t|int32_t)\s+(mps_[a-z_]+)\s*\("
+    decl = r"^\s*(?:mps_status|void|const char\s*\*|int64_t|int32_t)\s+(mps_[a-z0-9_]+)\s*\("
     return sorted(set(re.findall(decl, text, flags=re.M)))
 
 
