@@ -391,6 +391,39 @@ def instances_phase(args):
     print(json.dumps(line), flush=True)
 
 
+def alg1_phase(args):
+    """Algorithm 1 (one Pauli string per group, 2 N_h reverse walks) against
+    back-propagation on the same plan: 6 qubits (3 orbitals, 2 electrons),
+    D = 8, no truncation, where both give the exact gradient."""
+    import numpy as np
+    from vqe_inputs import configs
+    from paper_2211_07983_amd import Context, Plan
+    prob, gates = configs.small(6, 2, 8, seed=1)
+    ctx = Context(0)
+    plan = Plan(ctx, prob.occ, gates, prob.n_qubits, prob.ham_x, prob.ham_z, prob.ham_c, prob.c0,
+                prob.bond_dim, prob.eps)
+    plan.energy_grad(prob.theta)                       # warm-up
+    t0 = time.perf_counter()
+    e_bp, g_bp, _ = plan.energy_grad(prob.theta)
+    t_bp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e_a1, g_a1, _, _ = plan.energy_grad_alg1(prob.theta)
+    t_a1 = time.perf_counter() - t0
+    diff = float(np.abs(g_a1 - g_bp).max() / np.abs(g_bp).max())
+    log(f"back-propagation {t_bp:.3f}s, Algorithm 1 {t_a1:.3f}s ({len(prob.ham_c)} strings), rel diff {diff:.1e}")
+    line = {
+        "metric": "gradient time, Algorithm 1 (one string per group) / back-propagation (same plan, one GPU)",
+        "value": t_a1 / t_bp, "unit": "ratio", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * t_a1, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"UCCSD-MPS 6 qubits (3 orbitals, 2 electrons), D=8, eps={prob.eps:g}, "
+                               f"{gates.n_gates} NN gates, {len(prob.ham_c)} Pauli strings, n_theta={prob.n_theta}",
+                   "t_backprop_s": t_bp, "t_alg1_s": t_a1, "max_rel_grad_diff": diff, "E": e_bp},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,7 +436,7 @@ def main():
     ap.add_argument("--ckpt-gates", type=int, default=512)
     ap.add_argument("--profile-every", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr", "vqe", "instances"], default="evalgrad")
+    ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr", "vqe", "instances", "alg1"], default="evalgrad")
     ap.add_argument("--class-qubits", type=int, default=12, help="--phase instances: qubit count of the class")
     ap.add_argument("--class-d", type=int, default=64, help="--phase instances: bond dimension of the class")
     ap.add_argument("--vqe-iters", type=int, default=100, help="--phase vqe: iteration limit")
@@ -433,6 +466,9 @@ def main():
         return
     if args.phase == "instances":
         instances_phase(args)
+        return
+    if args.phase == "alg1":
+        alg1_phase(args)
         return
     import numpy as np
     from vqe_inputs import configs

@@ -17,7 +17,7 @@ def test_every_phase_is_offered():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0
-    for phase in ("evalgrad", "sweep", "psr", "vqe", "instances"):
+    for phase in ("evalgrad", "sweep", "psr", "vqe", "instances", "alg1"):
         assert phase in r.stdout
 
 
