@@ -50,9 +50,10 @@ __global__ __launch_bounds__(256) void k_apply_pauli(MpsView st, unsigned long l
 // between two MPS of the same qubit count and capacity.  One work-group:
 // the mixed left environment through sites < n, the mixed right environment
 // through sites > n+1, and the two-site centre, each phase a strided loop over
-// its outputs.  work: 26 dcap^2 complex entries.  out[0] = the overlap.
+// its outputs.  work: 26 dcap^2 complex entries.  acc[0] += eta[0] * Re(the
+// overlap).
 __global__ __launch_bounds__(256) void k_overlap_op(MpsView phi, MpsView psi, int n, const zd* op, zd* work,
-                                                    zd* out) {
+                                                    const double* eta, double* acc) {
   const int t = threadIdx.x, dc = psi.dcap, N = psi.N;
   const size_t dd = (size_t)dc * dc;
   zd* L = work;
@@ -170,8 +171,13 @@ __global__ __launch_bounds__(256) void k_overlap_op(MpsView phi, MpsView psi, in
     }
     __syncthreads();
   }
-  if (t == 0) out[0] = zmk(red[0][0], red[1][0]);
+  if (t == 0) acc[0] += eta[0] * red[0][0];
 }
+
+// eta <- v (start of a walk) and eta <- eta * nu after each truncation of phi
+// (nu: the kept norm the SVD records in gdmeta[0]).
+__global__ void k_eta_set(double* eta, double v) { eta[0] = v; }
+__global__ void k_eta_scale(double* eta, const double* gdmeta) { eta[0] *= gdmeta[0]; }
 
 namespace {
 
@@ -270,11 +276,30 @@ void plan_energy_grad_alg1(mps_plan* p, const double* theta, int n_theta, int pe
   double ev[3];
   HIPCHK(hipMemcpyAsync(ev, ctx->sb.energy, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   read_stats(ctx, stats, G);   // synchronises
-  // reverse walks, one per string
+  // reverse walks, one per string; the walk runs on the stream without host
+  // synchronisation: eta and dE/dphi_g live on the device
   zd* work = (zd*)p->alg1_work.ensure((size_t)26 * dc * dc * sizeof(zd));
-  zd* opd = (zd*)p->alg1_op.ensure(16 * sizeof(zd) + 256);
-  zd* outd = opd + 16;
-  std::vector<double> gphi(std::max(1, G), 0.0);
+  double* etad = (double*)p->alg1_op.ensure(((size_t)std::max(1, G) + 1) * sizeof(double));
+  double* gphid = etad + 1;
+  zd* dq = (zd*)p->alg1_dq.ensure((size_t)std::max(1, G) * 16 * sizeof(zd));
+  std::vector<zd> dqh((size_t)std::max(1, G) * 16, zmk(0.0, 0.0));
+  for (int g = 0; g < G; ++g) {
+    if (p->C.kind_h[g] != 1) continue;
+    // dU/dphi = post (-i ZZ / 2) RZZ(phi) pre
+    const double ph = p->C.coeff_h[g] * theta[p->C.param_h[g]];
+    const cplx e = std::exp(cplx(0.0, -0.5 * ph));
+    const cplx d[4] = {cplx(0.0, -0.5) * e, cplx(0.0, 0.5) * std::conj(e), cplx(0.0, 0.5) * std::conj(e),
+                       cplx(0.0, -0.5) * e};
+    cplx P[16], Q[16], D[16] = {}, T1[16], dQ[16];
+    mat_of(post, g, P);
+    mat_of(pre, g, Q);
+    for (int i = 0; i < 4; ++i) D[i * 4 + i] = d[i];
+    matmul(D, Q, T1);
+    matmul(P, T1, dQ);
+    for (int i = 0; i < 16; ++i) dqh[(size_t)g * 16 + i] = zmk(dQ[i].real(), dQ[i].imag());
+  }
+  HIPCHK(hipMemcpyAsync(dq, dqh.data(), dqh.size() * sizeof(zd), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(gphid, 0, (size_t)std::max(1, G) * sizeof(double), s));
   const MpsView vphi = view_of(phi.get()), vpsi = view_of(psi.get());
   const dim3 pgrid((dc * dc + 255) / 256, N);
   for (int64_t k = 0; k < p->H.K; ++k) {
@@ -284,40 +309,21 @@ void plan_energy_grad_alg1(mps_plan* p, const double* theta, int n_theta, int pe
     copy_state(psi.get(), psiM.get(), s);
     hipLaunchKernelGGL(k_apply_pauli, pgrid, dim3(256), 0, s, vphi, (unsigned long long)p->H.xs[k],
                        (unsigned long long)p->H.zs[k]);
+    hipLaunchKernelGGL(k_eta_set, dim3(1), dim3(1), 0, s, etad, 2.0 * ck);
     HIPCHK(hipGetLastError());
-    double eta = 2.0 * ck;
     for (int g = G - 1; g >= 0; --g) {
       const int gi = G - 1 - g, n = p->C.bond_h[g];
       run_gates(psi.get(), p->Cinv, th, gi, gi + 1, GATE_TAPE);
-      if (p->C.kind_h[g] == 1) {
-        // dU/dphi = post (-i ZZ / 2) RZZ(phi) pre
-        const double ph = p->C.coeff_h[g] * theta[p->C.param_h[g]];
-        const cplx e = std::exp(cplx(0.0, -0.5 * ph));
-        const cplx d[4] = {cplx(0.0, -0.5) * e, cplx(0.0, 0.5) * std::conj(e), cplx(0.0, 0.5) * std::conj(e),
-                           cplx(0.0, -0.5) * e};
-        cplx P[16], Q[16], D[16] = {}, T1[16], dQ[16];
-        mat_of(post, g, P);
-        mat_of(pre, g, Q);
-        for (int i = 0; i < 4; ++i) D[i * 4 + i] = d[i];
-        matmul(D, Q, T1);
-        matmul(P, T1, dQ);
-        zd opz[16];
-        for (int i = 0; i < 16; ++i) opz[i] = zmk(dQ[i].real(), dQ[i].imag());
-        zd res;
-        HIPCHK(hipMemcpyAsync(opd, opz, sizeof(opz), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_overlap_op, dim3(1), dim3(256), 0, s, vphi, vpsi, n, (const zd*)opd, work, outd);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&res, outd, sizeof(zd), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));   // opz and res are on this frame
-        gphi[g] += eta * res.x;
-      }
+      if (p->C.kind_h[g] == 1)
+        hipLaunchKernelGGL(k_overlap_op, dim3(1), dim3(256), 0, s, vphi, vpsi, n, (const zd*)(dq + (size_t)g * 16),
+                           work, (const double*)etad, gphid + g);
       run_gates(phi.get(), p->Cinv, th, gi, gi + 1, GATE_TAPE);
-      double nu = 1.0;
-      HIPCHK(hipMemcpyAsync(&nu, ctx->gw.gdmeta, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      eta *= nu;
+      hipLaunchKernelGGL(k_eta_scale, dim3(1), dim3(1), 0, s, etad, (const double*)ctx->gw.gdmeta);
     }
+    HIPCHK(hipGetLastError());
   }
+  std::vector<double> gphi(std::max(1, G), 0.0);
+  HIPCHK(hipMemcpyAsync(gphi.data(), gphid, gphi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   read_stats(ctx, nullptr, 0);   // fails on a barrier timeout or a non-converged SVD of the walks
   *energy = ev[0];
   if (n_theta > 0) {

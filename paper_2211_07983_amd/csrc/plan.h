@@ -110,7 +110,7 @@ struct mps_plan {
   DevCircuit C;
   DevCircuit Cinv;                 // the circuit's inverse (Algorithm 1's reverse walk)
   bool cinv_built = false;
-  DevBuf alg1_work, alg1_op;       // overlap workspace and operator of the reverse walk
+  DevBuf alg1_work, alg1_op, alg1_dq;   // overlap workspace, eta and dE/dphi, derivative operators
   DevHamiltonian H;
   DevBuf theta, grad, gphi;
   DevBuf ckpt;                     // [n_seg][B | dims | lam] snapshots
