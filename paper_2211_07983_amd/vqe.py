@@ -51,6 +51,8 @@ def _stop(e_prev, e, g, e_tol, g_tol):
 
 def gradient_descent(fg, theta0, lr=0.05, max_iter=MAX_ITER, e_tol=E_TOL, g_tol=G_TOL):
     """theta <- theta - lr * grad with a fixed step.  fg(theta) -> (E, grad)."""
+    if lr <= 0.0:
+        raise ValueError("lr must be > 0")
     th = np.array(theta0, dtype=np.float64)
     e, g = fg(th)
     res = Result(th, e, g, 0, "max_iter", [e], [float(np.linalg.norm(g))], 1)
@@ -72,6 +74,8 @@ def gradient_descent(fg, theta0, lr=0.05, max_iter=MAX_ITER, e_tol=E_TOL, g_tol=
 
 def adam(fg, theta0, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, max_iter=MAX_ITER, e_tol=E_TOL, g_tol=G_TOL):
     """Adam with bias-corrected first and second moments."""
+    if lr <= 0.0 or not 0.0 <= beta1 < 1.0 or not 0.0 <= beta2 < 1.0:
+        raise ValueError("need lr > 0 and 0 <= beta1, beta2 < 1")
     th = np.array(theta0, dtype=np.float64)
     e, g = fg(th)
     res = Result(th, e, g, 0, "max_iter", [e], [float(np.linalg.norm(g))], 1)
@@ -108,6 +112,8 @@ def bfgs(fg, theta0, fg_batched=None, n_trial=4, shrink=0.5, c1=1e-4, max_step=1
     a_i with E(a_i) <= E + c1 a_i (g.p) is taken; if none qualifies the search
     restarts from the smallest trial step with the Hessian reset to the
     identity, and a second failure ends the run ("line_search")."""
+    if n_trial < 1 or not 0.0 < shrink < 1.0 or not 0.0 < c1 < 1.0 or max_step <= 0.0:
+        raise ValueError("need n_trial >= 1, 0 < shrink < 1, 0 < c1 < 1 and max_step > 0")
     th = np.array(theta0, dtype=np.float64)
     n = th.size
     e, g = fg(th)

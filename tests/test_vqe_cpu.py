@@ -100,3 +100,13 @@ def test_bfgs_vqe_on_8_qubits_respects_the_variational_bound():
     assert all(e1 <= e0_ + 1e-14 for e0_, e1 in zip(r.energies, r.energies[1:]))
     assert r.energy >= e0 - 1e-9
     assert r.energy < e_hf
+
+
+def test_invalid_settings_are_refused():
+    A, b, xs, fg = quadratic()
+    with pytest.raises(ValueError):
+        vqe.bfgs(fg, np.zeros(6), n_trial=0)
+    with pytest.raises(ValueError):
+        vqe.gradient_descent(fg, np.zeros(6), lr=0.0)
+    with pytest.raises(ValueError):
+        vqe.adam(fg, np.zeros(6), beta1=1.0)
