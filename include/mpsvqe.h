@@ -202,20 +202,24 @@ mps_status mps_energy_grad_batched(mps_plan* plan, int32_t n_batch, const double
 
 /* Gradient by the paper's memory-efficient back-propagation (Sec. 4,
  * Algorithm 1) with the Hamiltonian split into groups of strings_per_group
- * Pauli strings; only strings_per_group = 1 (m = N_h groups) is supported, so
- * each group state phi_k = 2 c_k P_k Psi_M is an exact MPS of Psi_M's bonds
- * and needs no compression.  Per string the circuit is walked backwards with
- * two states (Psi <- U^dagger Psi; dE/dphi_g += Re <phi|dU_g/dphi_g|Psi>;
- * phi <- U^dagger phi), each step the forward gate update with the plan's
+ * consecutive Pauli strings.  With one string per group (m = N_h) each group
+ * state phi_k = 2 c_k P_k Psi_M is an exact MPS of Psi_M's bonds; with more,
+ * phi_j = 2 sum_k c_k P_k Psi_M is built as a direct sum and compressed to the
+ * plan's truncation (QR sweep from the left, truncated SVD sweep from the
+ * right, then a lossless pair of sweeps for exact Schmidt values), which needs
+ * strings_per_group * bond capacity <= 128.  Per group the circuit is walked
+ * backwards with two states (Psi <- U^dagger Psi;
+ * dE/dphi_g += Re <phi|dU_g/dphi_g|Psi>; phi <- U^dagger phi), each step the
+ * forward gate update with the plan's
  * truncation; Psi stays normalised and phi keeps its norm (each truncation
  * scales it by the kept norm).  Without truncation the result is the exact
  * gradient at every theta, including theta = 0 where mps_energy_grad's local
  * gradient of the truncated evolution vanishes; with truncation it is the
- * global approximation the paper uses.  Costs 2 N_h passes over the circuit.
+ * global approximation the paper uses.  Costs 2 m passes over the circuit.
  * theta, grad: host [n_theta]; energy: E(theta); gate_grad (nullable): host
  * [n_gates], dE/dphi_g for PARAM gates and 0 for FIXED ones; stats: the
- * forward pass's.  strings_per_group != 1: MPS_EINVAL; other errors as
- * mps_energy_grad.                                                          */
+ * forward pass's.  strings_per_group < 1 or above the limit: MPS_EINVAL;
+ * other errors as mps_energy_grad.                                          */
 mps_status mps_energy_grad_alg1(mps_plan* plan, const double* theta, int32_t n_theta, int32_t strings_per_group,
                                 double* energy, double* grad, double* gate_grad, mps_stats* stats);
 

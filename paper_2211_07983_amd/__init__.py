@@ -293,7 +293,8 @@ class Plan:
         return e.value, g[:len(th)], gg[:self.n_gates], s.as_dict()
 
     def energy_grad_alg1(self, theta, strings_per_group=1):
-        """Gradient by the paper's Algorithm 1 with one Pauli string per group:
+        """Gradient by the paper's Algorithm 1 with the Hamiltonian split into
+        groups of strings_per_group strings (mps_energy_grad_alg1):
         (E, grad [n_theta], dE/dphi per gate [n_gates], stats)."""
         th = np.ascontiguousarray(theta, dtype=np.float64)
         e = C.c_double()

@@ -111,6 +111,7 @@ struct mps_plan {
   DevCircuit Cinv;                 // the circuit's inverse (Algorithm 1's reverse walk)
   bool cinv_built = false;
   DevBuf alg1_work, alg1_op, alg1_dq;   // overlap workspace, eta and dE/dphi, derivative operators
+  DevBuf alg1_terms, alg1_cws;          // string masks and weights, compression workspace
   DevHamiltonian H;
   DevBuf theta, grad, gphi;
   DevBuf ckpt;                     // [n_seg][B | dims | lam] snapshots

@@ -1,9 +1,10 @@
-"""The paper's Algorithm 1 (Sec. 4) on the GPU, one Pauli string per group
-(mps_energy_grad_alg1), against the Algorithm 1 oracle with the same
-grouping and against the exact sector gradient: on 6 qubits without
-truncation (D = 8) at the seeded theta and at theta = 0, where the local
-gradient of mps_energy_grad vanishes, and with truncation (D = 2, every cut
-at least 4.6e-4 away from a degenerate pair, so the truncation is unique)."""
+"""The paper's Algorithm 1 (Sec. 4) on the GPU (mps_energy_grad_alg1), with
+one and with four Pauli strings per group, against the Algorithm 1 oracle
+with the same grouping and against the exact sector gradient: on 6 qubits
+without truncation (D = 8) at the seeded theta and at theta = 0, where the
+local gradient of mps_energy_grad vanishes, and with truncation (D = 2,
+every cut at least 4.6e-4 away from a degenerate pair, so the truncation is
+unique)."""
 import numpy as np
 import pytest
 
@@ -65,10 +66,41 @@ def test_truncating_regime_matches_oracle(setup):
     plan.free()
 
 
-def test_only_single_string_groups(setup):
+def test_groups_of_four_strings_exact(setup):
+    """N_h / m = 4 (the paper's setting): each group state is the compressed
+    direct sum of four Pauli images; without truncation the gradient is exact."""
+    from oracle import alg1
+    from oracle import sector as sec
+    ctx, p, g = setup
+    plan = plan_of(ctx, p, g, 8)
+    _, grad, gphi, _ = plan.energy_grad_alg1(p.theta, strings_per_group=4)
+    exact = sec.UCCSD(p).gradient(p.theta)
+    ref_phi, _ = alg1.gate_gradient(p, g, p.theta, alg1.split(len(p.ham_c), 4), D=8, eps=p.eps)
+    print(f"4 per group, D=8: vs exact {rel(grad, exact):.1e}, per gate vs oracle {np.abs(gphi - ref_phi).max():.1e}")
+    assert rel(grad, exact) <= 1e-8
+    assert np.abs(gphi - ref_phi).max() <= 1e-9 * np.abs(ref_phi).max()
+    plan.free()
+
+
+def test_groups_of_four_strings_truncating(setup):
+    """D = 2 on the first 24 strings (6 groups; every cut of the compressions
+    and walks at least 4.6e-4 from a degenerate pair)."""
+    from oracle import alg1
+    from paper_2211_07983_amd import Plan
+    ctx, p, g = setup
+    plan = Plan(ctx, p.occ, g, p.n_qubits, p.ham_x[:24], p.ham_z[:24], p.ham_c[:24], p.c0, 2, p.eps)
+    _, grad, gphi, _ = plan.energy_grad_alg1(p.theta, strings_per_group=4)
+    ref_phi, _ = alg1.gate_gradient(p, g, p.theta, alg1.split(24, 4), D=2, eps=p.eps)
+    print(f"4 per group, D=2: per gate vs oracle {np.abs(gphi - ref_phi).max():.1e} (max {np.abs(ref_phi).max():.3f})")
+    assert np.abs(gphi - ref_phi).max() <= 1e-9 * np.abs(ref_phi).max()
+    plan.free()
+
+
+def test_group_size_limits(setup):
     from paper_2211_07983_amd import MPSError
     ctx, p, g = setup
     plan = plan_of(ctx, p, g, 8)
-    with pytest.raises(MPSError):
-        plan.energy_grad_alg1(p.theta, strings_per_group=4)
+    for bad in (0, 17):             # 17 strings x capacity 8 > 128
+        with pytest.raises(MPSError):
+            plan.energy_grad_alg1(p.theta, strings_per_group=bad)
     plan.free()
