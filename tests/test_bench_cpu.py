@@ -36,3 +36,19 @@ def test_instance_classes_share_their_circuit():
     for g in lists[1:]:
         for k in ("bond", "kind", "pre", "post", "param", "coeff"):
             assert np.array_equal(np.asarray(getattr(g, k)), np.asarray(getattr(lists[0], k)))
+
+
+def test_cpu_baseline_reports_both_thread_settings_and_the_host():
+    """The CPU baseline times the oracle with BLAS on one thread and on the
+    nproc setting, and records the host's core counts and CPU model."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from vqe_inputs import configs
+    p, g = configs.load("c1")
+    r = bench.cpu_baseline_settings(p, g, p.eps, full=True)
+    assert r["kind"] == "oracle" and r["unit"] == "evals/s" and r["value"] > 0
+    assert r["settings"][0]["cores"] == 1
+    assert r["cores"] in [s["cores"] for s in r["settings"]]
+    assert r["value"] == max(s["value"] for s in r["settings"])
+    host = r["host"]
+    assert host["nproc"] >= 1 and host["usable_cpus"] >= 1 and "cpu_model" in host
