@@ -24,8 +24,14 @@ a complex array X is defined by dF = Re <X_bar, dX> = Re sum conj(X_bar) dX,
 which is the paper's 2 dF/dX* convention (Eqs. bp1-bp4).  The truncated SVD
 is differentiated with its full spectrum: kept singular triplets couple to
 discarded ones and to the null space through F_ij = 1/(s_j^2 - s_i^2), plus
-the imaginary diagonal gauge term of the complex SVD.  No broadening is
-applied; a near-degenerate pair that carries a cotangent raises.
+the imaginary diagonal gauge term of the complex SVD.  By default no
+broadening is applied and a near-degenerate pair that carries a cotangent
+raises.  With broaden = eta > 0 every such factor becomes the Lorentzian
+d / (d^2 + eta^2), d = s_j^2 - s_i^2 (the regularisation of the SVD
+derivative used in the tensor-network AD literature the paper builds on,
+e.g. Liao et al. 2019): it is finite for every d, close to 1/d for
+|d| >> eta and zero at d = 0, so a (near-)degenerate pair is then dropped
+instead of raising.
 """
 from __future__ import annotations
 
@@ -191,8 +197,9 @@ class MPS:
         return E, Bbar
 
 
-def gate_backward(t, Q, dQ, Bbar_l, Bbar_r, lbar, check=1e-10):
-    """Cotangents of (B_n, B_{n+1}, lambda_{n-1}) and dE/dphi for one gate."""
+def gate_backward(t, Q, dQ, Bbar_l, Bbar_r, lbar, check=1e-10, broaden=0.0):
+    """Cotangents of (B_n, B_{n+1}, lambda_{n-1}) and dE/dphi for one gate;
+    broaden = eta of the Lorentzian factor (0: the plain 1/d)."""
     Bl, Br, lam_in, Theta, Cm = t["Bl"], t["Br"], t["lam_in"], t["Theta"], t["Cm"]
     U, s, Wh, r, nu, newBl = t["U"], t["s"], t["Wh"], t["r"], t["nu"], t["newBl"]
     a, _, m = Bl.shape
@@ -229,10 +236,14 @@ def gate_backward(t, Q, dQ, Bbar_l, Bbar_r, lbar, check=1e-10):
     # block, so its A_ij vanishes and the term is dropped; a degenerate pair
     # with a real cotangent has no finite derivative and raises.
     deg = active & (np.abs(sj - si) < check * np.maximum(si, sj))
-    if np.any(deg & (np.abs(A[:p, :]) > 1e-8 * kscale)):
+    if broaden <= 0.0 and np.any(deg & (np.abs(A[:p, :]) > 1e-8 * kscale)):
         raise SVDDegenerate("degenerate singular pair carries a cotangent")
     use = active & ~deg & (num != 0)
-    den = np.where(use, sj ** 2 - si ** 2, 1.0)
+    d = sj ** 2 - si ** 2
+    if broaden > 0.0:
+        den = np.where(use, (d * d + broaden * broaden) / np.where(use, d, 1.0), 1.0)
+    else:
+        den = np.where(use, d, 1.0)
     Gam = np.where(use, num / den, 0.0).astype(np.complex128)
     for i in range(r):
         Gam[i, i] = sbar[i] - 1j * K[i, i].imag / s[i]
@@ -286,8 +297,9 @@ def energy(prob, gates, theta, D=None, eps=None, ranks=None):
                    ranks=mps.ranks, mps=mps, degenerate_cuts=mps.degenerate_cuts)
 
 
-def energy_grad(prob, gates, theta, D=None, eps=None, ckpt=64, check=1e-10):
-    """(E, dE/dtheta, info) by reverse mode with segment checkpoints and recompute."""
+def energy_grad(prob, gates, theta, D=None, eps=None, ckpt=64, check=1e-10, broaden=0.0):
+    """(E, dE/dtheta, info) by reverse mode with segment checkpoints and recompute;
+    broaden = eta of the SVD adjoint's Lorentzian (0: none)."""
     D = prob.bond_dim if D is None else D
     eps = prob.eps if eps is None else eps
     snaps = []
@@ -309,7 +321,7 @@ def energy_grad(prob, gates, theta, D=None, eps=None, ckpt=64, check=1e-10):
             t = tape[g - g0]
             n = t["n"]
             Q, dQ = gate_mats(gates, g, theta)
-            bl, br, li, dphi = gate_backward(t, Q, dQ, Bbar[n], Bbar[n + 1], lbar[n + 1], check)
+            bl, br, li, dphi = gate_backward(t, Q, dQ, Bbar[n], Bbar[n + 1], lbar[n + 1], check, broaden)
             Bbar[n], Bbar[n + 1] = bl, br
             lbar[n + 1] = 0.0
             lbar[n] = lbar[n] + li

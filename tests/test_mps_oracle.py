@@ -95,3 +95,42 @@ def test_truncating_gradient_directional_fd(seed):
             return (ep - em) / (2 * h)
         fd = (4 * d(5e-4) - d(1e-3)) / 3
         assert abs(fd - grad @ v) <= 1e-7 * max(1.0, np.linalg.norm(grad))
+
+
+@pytest.mark.parametrize("seed", [1, 3])
+def test_broadened_svd_adjoint_limits(seed):
+    """The Lorentzian d/(d^2 + eta^2) replaces 1/d in the SVD adjoint: eta = 0
+    is the plain derivative bit for bit; for eta far below every squared gap
+    that carries a cotangent the change is -eta^2 sum c/d^3 + O(eta^4), so it
+    falls by 4 when eta halves and vanishes with eta (the plain derivative is
+    the one the directional finite differences above pin)."""
+    p, g = configs.small(8, 4, 6, seed=seed, theta_sigma=0.3)
+    _, g0, _ = mps.energy_grad(p, g, p.theta)
+    _, gz, _ = mps.energy_grad(p, g, p.theta, broaden=0.0)
+    assert np.array_equal(g0, gz)
+    dev = []
+    for eta in (4e-10, 2e-10, 1e-10):
+        _, ge, _ = mps.energy_grad(p, g, p.theta, broaden=eta)
+        dev.append(np.abs(ge - g0).max() / np.abs(g0).max())
+    assert 0 < dev[2] < 1e-7
+    for a, b in zip(dev, dev[1:]):
+        assert 3.9 <= a / b <= 4.1
+    # and it is a real change at larger eta: pairs with squared gaps near 1e-8
+    _, ge, _ = mps.energy_grad(p, g, p.theta, broaden=1e-8)
+    assert np.abs(ge - g0).max() > 1e-6 * np.abs(g0).max()
+
+
+def test_degenerate_cut_raises_unless_broadened():
+    """A truncation through an exactly degenerate pair that carries a cotangent
+    has no fixed-rank derivative: the plain adjoint raises; the broadened one
+    drops the pair (the Lorentzian is zero at d = 0) and stays finite."""
+    import degenerate_case as dc
+    p, g = dc.problem()
+    _, info = mps.energy(p, g, p.theta)
+    assert info["degenerate_cuts"] == 1 and abs(info["discarded"][0] - 0.5) < 1e-12
+    with pytest.raises(mps.SVDDegenerate):
+        mps.energy_grad(p, g, p.theta)
+    _, gb, _ = mps.energy_grad(p, g, p.theta, broaden=1e-6)
+    assert np.all(np.isfinite(gb))
+    # away from the degeneracy the same circuit has a derivative again
+    mps.energy_grad(p, g, p.theta + 0.3)
