@@ -271,6 +271,21 @@ mps_status mps_plan_energy(mps_plan* plan, const double* theta, int32_t n_theta,
  * packed per site in site order; lam: host double [n_qubits+1][d_max].      */
 mps_status mps_state_export(const mps_state* st, int32_t* dims, double* B, double* lam);
 int64_t mps_state_size(const mps_state* st);   /* doubles needed by B above */
+/* Test access, the inverse of mps_state_export: a new state on ctx from host
+ * copies of an MPS in the form of Sec. 3 (site tensors B_n[alpha][i][beta]
+ * and the Schmidt vectors lambda_k of Eq. rightcanonicalcondition), so that
+ * the expectation (Eq. paulistringexp) and the gate update can be checked on
+ * states built elsewhere.  dims: [n_qubits+1] with dims[0] = dims[n_qubits]
+ * = 1 and 1 <= dims[k] <= trunc->d_max; B: complex [n][dims[n]][2][dims[n+1]]
+ * packed per site in site order (mps_state_export's layout, mps_state_size
+ * doubles); lam: packed, dims[k] values for each k = 0..n_qubits.  The
+ * tensors need not be canonical or normalised: mps_expect_paulisum divides
+ * by <psi|psi>; the gate update weights with lam as given.  trunc: the
+ * truncation of later updates, as in mps_init_product.  The arrays are read
+ * during the call only.  Bad sizes, NULL or non-finite input: MPS_EINVAL,
+ * nothing allocated.                                                       */
+mps_status mps_state_import(mps_ctx* ctx, int32_t n_qubits, const mps_trunc* trunc, const int32_t* dims,
+                            const double* B, const double* lam, mps_state** out);
 int32_t mps_state_qubits(const mps_state* st);
 
 void mps_state_free(mps_state* st);

@@ -154,6 +154,21 @@ class State:
         ctx.check(ctx._lib.mps_init_product(ctx.h, len(occ), _ptr(occ, C.c_uint8), C.byref(tr), C.byref(h)))
         return cls(ctx, h, len(occ), d_max)
 
+    @classmethod
+    def from_tensors(cls, ctx, tensors, lams, d_max, eps, precision=0):
+        """mps_state_import: tensors[n] complex [dl, 2, dr], lams[k] the Schmidt
+        vector left of site k (k = 0..n)."""
+        n = len(tensors)
+        dims = np.array([1] + [int(t.shape[2]) for t in tensors], dtype=np.int32)
+        B = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.complex128).ravel() for t in tensors]))
+        lam = np.ascontiguousarray(np.concatenate([np.asarray(l, dtype=np.float64).ravel() for l in lams]))
+        tr = Trunc(int(d_max), float(eps), int(precision))
+        h = C.c_void_p()
+        ctx.check(ctx._lib.mps_state_import(ctx.h, n, C.byref(tr), _ptr(dims, C.c_int32),
+                                            _ptr(B.view(np.float64), C.c_double), _ptr(lam, C.c_double),
+                                            C.byref(h)))
+        return cls(ctx, h, n, d_max)
+
     def apply_circuit(self, gates, theta):
         args = _CircuitArgs(gates)
         th = np.ascontiguousarray(theta, dtype=np.float64)

@@ -16,7 +16,7 @@ EXPORTS = [
     "mps_apply_circuit", "mps_expect_paulisum", "mps_plan_create", "mps_energy_grad",
     "mps_energy_grad_batched", "mps_energy_grad_multi", "mps_plan_batch_width", "mps_energy_grad_psr",
     "mps_energy_grad_alg1",
-    "mps_plan_energy", "mps_state_export", "mps_state_size", "mps_state_qubits",
+    "mps_plan_energy", "mps_state_export", "mps_state_import", "mps_state_size", "mps_state_qubits",
     "mps_state_free", "mps_plan_free",
 ]
 
@@ -121,6 +121,9 @@ def load(path=LIB_PATH):
     lib.mps_plan_energy.restype = C.c_int32
     lib.mps_state_export.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.mps_state_export.restype = C.c_int32
+    lib.mps_state_import.argtypes = [vp, C.c_int32, C.POINTER(Trunc), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(vp)]
+    lib.mps_state_import.restype = C.c_int32
     lib.mps_state_size.argtypes = [vp]
     lib.mps_state_size.restype = C.c_int64
     lib.mps_state_qubits.argtypes = [vp]

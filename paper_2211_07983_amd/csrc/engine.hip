@@ -600,6 +600,59 @@ mps_status mps_state_export(const mps_state* st, int32_t* dims, double* B, doubl
   });
 }
 
+mps_status mps_state_import(mps_ctx* ctx, int32_t n_qubits, const mps_trunc* trunc, const int32_t* dims,
+                            const double* B, const double* lam, mps_state** out) {
+  if (!ctx || !out) return MPS_EINVAL;
+  return guarded(ctx, [&] {
+    if (n_qubits < 2 || n_qubits > 64) fail(MPS_EINVAL, "n_qubits must be in [2, 64]");
+    if (!trunc || !dims || !B || !lam) fail(MPS_EINVAL, "NULL argument");
+    if (trunc->d_max < 1 || trunc->d_max > 256) fail(MPS_EINVAL, "d_max must be in [1, 256]");
+    if (!(trunc->eps >= 0.0) || !std::isfinite(trunc->eps)) fail(MPS_EINVAL, "eps must be finite and >= 0");
+    if (trunc->precision != 0 && trunc->precision != 1) fail(MPS_EINVAL, "precision must be 0 or 1");
+    const int N = n_qubits;
+    if (dims[0] != 1 || dims[N] != 1) fail(MPS_EINVAL, "dims[0] and dims[n_qubits] must be 1");
+    for (int k = 1; k < N; ++k)
+      if (dims[k] < 1 || dims[k] > trunc->d_max) fail(MPS_EINVAL, "bond dimension outside [1, d_max]");
+    size_t nb = 0, nl = 0;
+    for (int n = 0; n < N; ++n) nb += (size_t)2 * dims[n] * dims[n + 1];
+    for (int k = 0; k <= N; ++k) nl += (size_t)dims[k];
+    for (size_t i = 0; i < 2 * nb; ++i)
+      if (!std::isfinite(B[i])) fail(MPS_EINVAL, "non-finite site tensor entry");
+    for (size_t i = 0; i < nl; ++i)
+      if (!std::isfinite(lam[i]) || lam[i] < 0.0) fail(MPS_EINVAL, "Schmidt values must be finite and >= 0");
+    mps_state* st = new mps_state();
+    try {
+      st->ctx = ctx;
+      st->N = N;
+      st->trunc = *trunc;
+      st->dcap = std::max(2, ((trunc->d_max + 1) / 2) * 2);
+      const int dc = st->dcap;
+      alloc_state(st);
+      // scatter into the capacity layout on the host, then one upload per array
+      std::vector<zd> all((size_t)N * dc * 2 * dc, zmk(0.0, 0.0));
+      size_t o = 0;
+      for (int n = 0; n < N; ++n)
+        for (int al = 0; al < dims[n]; ++al)
+          for (int i = 0; i < 2; ++i)
+            for (int be = 0; be < dims[n + 1]; ++be, o += 2)
+              all[(size_t)n * dc * 2 * dc + (size_t)al * 2 * dc + i * dc + be] = zmk(B[o], B[o + 1]);
+      std::vector<double> l((size_t)(N + 1) * dc, 0.0);
+      o = 0;
+      for (int k = 0; k <= N; ++k)
+        for (int j = 0; j < dims[k]; ++j) l[(size_t)k * dc + j] = lam[o++];
+      std::vector<int> d(dims, dims + N + 1);
+      HIPCHK(hipMemcpyAsync(st->B.p, all.data(), all.size() * sizeof(zd), hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(st->lam.p, l.data(), l.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(st->dims.p, d.data(), d.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));   // the host vectors are released at the end of this block
+    } catch (...) {
+      delete st;
+      throw;
+    }
+    *out = st;
+  });
+}
+
 int64_t mps_state_size(const mps_state* st) {
   if (!st) return -1;
   std::vector<int> d(st->N + 1);
