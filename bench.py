@@ -98,8 +98,13 @@ def host_info():
         usable = len(os.sched_getaffinity(0))
     except AttributeError:
         usable = os.cpu_count() or 1
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [f"{d.get('internal_api')}:{d.get('num_threads')}" for d in threadpool_info()]
+    except Exception:
+        libs = []
     return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model,
-            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "thread_pools": libs}
 
 
 def nproc_threads():
@@ -138,16 +143,19 @@ def cpu_baseline_settings(prob, gates, eps, full):
     from threadpoolctl import threadpool_limits
     runs = []
     for n in (1, nproc_threads()):
-        if runs and n == runs[0]["cores"]:
+        if runs and n == runs[0]["requested_threads"]:
             break
-        with threadpool_limits(n):
+        with threadpool_limits(limits=n):
             r = cpu_baseline_full(prob, gates, eps) if full else cpu_baseline_sample(prob, gates, eps)
-        log(f"cpu baseline, {r['cores']} BLAS thread(s): {r['value']:.3e} evals/s ({r['seconds_per_eval']:.1f} s/eval)")
+            r["thread_pools"] = host_info()["thread_pools"]
+        r["requested_threads"] = n
+        log(f"cpu baseline, {n} requested / {r['cores']} reported BLAS thread(s): {r['value']:.3e} evals/s "
+            f"({r['seconds_per_eval']:.1f} s/eval); pools {r['thread_pools']}")
         runs.append(r)
     best = max(runs, key=lambda r: r["value"])
     out = dict(best)
-    out["settings"] = [{"cores": r["cores"], "value": r["value"], "seconds_per_eval": r["seconds_per_eval"]}
-                       for r in runs]
+    out["settings"] = [{"cores": r["cores"], "requested_threads": r["requested_threads"], "value": r["value"],
+                        "seconds_per_eval": r["seconds_per_eval"], "thread_pools": r["thread_pools"]} for r in runs]
     out["host"] = host_info()
     return out
 
@@ -591,8 +599,9 @@ def main():
     step_est = t_single * max(1.0, nb / 8.0)    # a first guess until a batched step has run
     warm_done = 0
     for w in range(args.warmup):
-        # warm-ups after the first only while a timed step would still fit behind them
-        if w > 0 and not fits(2 * step_est):
+        # warm-ups after the first only when every requested timed step still
+        # fits behind the remaining ones: timed steps come first
+        if w > 0 and not fits((args.warmup - w + args.steps) * step_est):
             break
         if not fits(step_est):
             break

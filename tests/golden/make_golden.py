@@ -93,9 +93,83 @@ def batched_instance(i):
                 discarded_sum=float(sum(finfo["discarded"])))
 
 
+# Truncating instances of the batched set at the paper's threshold eps = 1e-6
+# whose cuts never fall inside a degenerate pair (the oracle's degenerate-cut
+# count is zero), so E_D and g_D are unique; found by running the oracle over
+# the set's 12- and 16-qubit instances.
+C4_PARITY = (3, 8, 14, 17)
+
+
+def batched_instance_paper(i):
+    """Instance i of the batched set at eps = 1e-6: energy, gradient, bonds,
+    discarded weight and the degenerate-cut count of the forward pass."""
+    from vqe_inputs.compile import compile_problem
+    from vqe_inputs.problem import make_problem
+    n, ne, D, s1, s2 = configs.batched_instances()[i]
+    p = make_problem(f"c4_{i}", n, ne, D, configs.PAPER_EPS, s1, s2, 0.05)
+    g = compile_problem(p)
+    E, grad, info = mps.energy_grad(p, g, p.theta)
+    _, finfo = mps.energy(p, g, p.theta)
+    return dict(n_qubits=n, D=D, eps=p.eps, E=E, grad=grad.tolist(), bonds=finfo["bonds"],
+                discarded_sum=float(sum(finfo["discarded"])), degenerate_cuts=int(finfo["degenerate_cuts"]),
+                n_gates=int(g.n_gates))
+
+
+C5_GRAD_PREFIX = 2000
+C5_TERM_STRIDE = 100
+C5_CKPT_GATES = 426   # 8 compiled rotation blocks on average (690k gates / 12960 rotations * 8)
+
+
+def c5_prefix_grad():
+    """Energy and gradient of the first C5_GRAD_PREFIX gates of the 40-qubit,
+    D=256 workload for every C5_TERM_STRIDE-th Pauli term, with checkpoints
+    every C5_CKPT_GATES gates."""
+    import dataclasses
+    p, g = configs.load("c5")
+    G = C5_GRAD_PREFIX
+    pre = dataclasses.replace(g, bond=g.bond[:G], kind=g.kind[:G], pre=g.pre[:G], post=g.post[:G],
+                              param=g.param[:G], coeff=g.coeff[:G])
+    sub = slice(0, None, C5_TERM_STRIDE)
+    ps = dataclasses.replace(p, ham_x=p.ham_x[sub], ham_z=p.ham_z[sub], ham_c=p.ham_c[sub])
+    n_theta = int(pre.param.max()) + 1
+    E, grad, info = mps.energy_grad(ps, pre, p.theta, ckpt=C5_CKPT_GATES)
+    _, finfo = mps.energy(ps, pre, p.theta)
+    return dict(gates=G, term_stride=C5_TERM_STRIDE, ckpt_gates=C5_CKPT_GATES, n_terms=int(len(ps.ham_c)),
+                n_theta=n_theta, E=E, grad=grad[:n_theta].tolist(), bonds=finfo["bonds"],
+                degenerate_cuts=int(finfo["degenerate_cuts"]))
+
+
+C2_BROADEN = 1e-8
+
+
+def c2_paper_broaden():
+    """C2 at eps = 1e-6 with the SVD adjoint's Lorentzian broadening eta =
+    C2_BROADEN, and the unbroadened gradient for comparison."""
+    p, g = configs.load("c2", eps=configs.PAPER_EPS)
+    E, grad, _ = mps.energy_grad(p, g, p.theta, broaden=C2_BROADEN)
+    return dict(eps=p.eps, broaden=C2_BROADEN, E=E, grad=grad.tolist())
+
+
+def alg1_c1_groups4():
+    """Algorithm 1 on the 8-qubit workload with capacity D = 32 (no truncation:
+    the largest Schmidt rank is 16) and four strings per group, so the
+    compressed group states reach the GPU compression's bound of
+    4 x 32 = 128: per-gate derivatives and the gradient, plus the exact one."""
+    from oracle import alg1
+    p, g = configs.load("c1")
+    gphi, _ = alg1.gate_gradient(p, g, p.theta, alg1.split(len(p.ham_c), 4), D=32, eps=p.eps)
+    grad = alg1.chain_rule(g, gphi, p.n_theta)
+    exact = sector.UCCSD(p).gradient(p.theta)
+    return dict(D=32, per_group=4, gphi=list(map(float, gphi)), grad=list(map(float, grad)),
+                grad_exact=exact.tolist())
+
+
 ENTRIES = {"c1": lambda: exact_config("c1"), "c2": lambda: exact_config("c2"), "c2_paper": c2_paper,
            "c3_prefix": c3_prefix, "c3_prefix_grad": c3_prefix_grad, "c5_prefix": c5_prefix,
-           "c4_3": lambda: batched_instance(3), "c4_4": lambda: batched_instance(4)}
+           "c4_3": lambda: batched_instance(3), "c4_4": lambda: batched_instance(4),
+           "c5_prefix_grad": c5_prefix_grad, "c2_paper_broaden": c2_paper_broaden,
+           "alg1_c1_groups4": alg1_c1_groups4}
+ENTRIES.update({f"c4p_{i}": (lambda i=i: batched_instance_paper(i)) for i in C4_PARITY})
 
 
 def main(names):

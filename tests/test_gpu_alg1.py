@@ -104,3 +104,28 @@ def test_group_size_limits(setup):
         with pytest.raises(MPSError):
             plan.energy_grad_alg1(p.theta, strings_per_group=bad)
     plan.free()
+
+
+def test_groups_of_four_strings_at_the_compression_bound():
+    """8 qubits (the 8-qubit workload, 360 strings, 90 groups of four) with
+    capacity D = 32: each compressed group state has bond capacity 4 x 32 =
+    128, the bound of the one-work-group compression, so its strided loops run
+    several iterations per thread.  The largest Schmidt rank is 16, so nothing
+    is truncated and the gradient is the exact one."""
+    from gpu_util import golden
+    from paper_2211_07983_amd import Context, Plan
+    p, g = configs.load("c1")
+    gold = golden()["alg1_c1_groups4"]
+    assert (gold["D"], gold["per_group"]) == (32, 4)
+    ctx = Context(0)
+    plan = Plan(ctx, p.occ, g, p.n_qubits, p.ham_x, p.ham_z, p.ham_c, p.c0, 32, p.eps)
+    _, grad, gphi, _ = plan.energy_grad_alg1(p.theta, strings_per_group=4)
+    ref_phi = np.array(gold["gphi"])
+    exact = np.array(gold["grad_exact"])
+    print(f"8 q, D=32, 4 per group: vs exact {rel(grad, exact):.1e}, per gate vs oracle "
+          f"{np.abs(gphi - ref_phi).max():.1e}")
+    assert rel(grad, exact) <= 1e-8
+    assert np.abs(gphi - ref_phi).max() <= 1e-9 * np.abs(ref_phi).max()
+    assert rel(grad, np.array(gold["grad"])) <= 1e-9
+    plan.free()
+    ctx.close()

@@ -3,15 +3,15 @@
 * 40 qubits (20 orbitals, 4 electrons), D = 256, 233000 Pauli terms: the
   state after the first 3000 gates (capacity 256: 4-column Jacobi blocks) and
   its energy over every term, in FP64 and in precision 1;
-* two instances of the batched set (qubits and D drawn per instance; here the
-  12-qubit ones at D = 32, which truncates, and D = 64, which is exact):
-  energy and gradient, single and batched.  Where the truncation at D cuts
-  through equal Schmidt values (degenerate cuts, reported by the stats), which
-  of them are kept is arbitrary and every choice is a valid truncation, so
-  E_D and g_D are not unique, and neither are the later states and their
-  truncation.  There the maximal bond is compared, the discarded weight is
-  checked loosely (within 10 %), and E_D is checked to lie within the bound
-  |dE| <= 2 sum_k |c_k| sqrt(discarded weight) that any two such choices obey.
+* five instances of the batched set (qubits and D drawn per instance): one
+  exact (12 q, D = 64) and four that truncate (12 q at D = 32 and 128, 16 q at
+  D = 32 and 64) at the paper's threshold eps = 1e-6: energy and gradient
+  against the oracle at 1e-10 and 1e-8, single and batched.  Where a
+  truncation at D cuts through equal Schmidt values, which of them are kept is
+  arbitrary and E_D and g_D are not unique; at the parity threshold 1e-12 the
+  set's truncating instances have such cuts among rounding-level values, at
+  1e-6 these four have none (the oracle's degenerate-cut count, asserted on
+  both sides).
 
 Expected values come from the oracle (tests/golden/make_golden.py)."""
 import numpy as np
@@ -55,33 +55,63 @@ def test_40_qubit_prefix_energy_matches_oracle(ctx):
     assert abs(e32 - e) <= 1e-6
 
 
-@pytest.mark.parametrize("i", [3, 4])
+@pytest.mark.parametrize("i", [4, 3, 8, 14, 17])
 def test_batched_set_instance_matches_oracle(ctx, i):
+    """Instance 4 (12 q, D = 64) is exact at the parity threshold; 3, 8, 14
+    and 17 (12 q at D = 32 and 128, 16 q at D = 32 and 64) truncate at the
+    paper's threshold eps = 1e-6 with no cut inside a degenerate pair (the
+    oracle's count is zero), so E_D and g_D are unique and compared strictly."""
     from paper_2211_07983_amd import Plan
     from vqe_inputs.compile import compile_problem
     from vqe_inputs.problem import make_problem
     n, ne, D, s1, s2 = configs.batched_instances()[i]
-    gold = golden()[f"c4_{i}"]
+    gold = golden()[f"c4_{i}" if i == 4 else f"c4p_{i}"]
     assert (gold["n_qubits"], gold["D"]) == (n, D)
-    p = make_problem(f"c4_{i}", n, ne, D, configs.PARITY_EPS, s1, s2, 0.05)
+    eps = gold.get("eps", configs.PARITY_EPS)
+    assert gold.get("degenerate_cuts", 0) == 0
+    p = make_problem(f"c4_{i}", n, ne, D, eps, s1, s2, 0.05)
     g = compile_problem(p)
     plan = Plan(ctx, p.occ, g, p.n_qubits, p.ham_x, p.ham_z, p.ham_c, p.c0, p.bond_dim, p.eps)
     e, grad, st = plan.energy_grad(p.theta)
-    print(f"instance {i}: {n} q, D={D}, truncated gates {st['gates_truncated']}, "
-          f"degenerate cuts {st['degenerate_cuts']}, E error {abs(e - gold['E']):.2e}")
-    assert st["max_bond"] == max(gold["bonds"])
     _, fst = plan.energy(p.theta)
     disc = fst["discarded_weight_sum"]
-    # cuts counted as degenerate among rounding-level values (total discarded
-    # weight below 1e-12) truncate nothing physical: the strict comparison holds
-    if st["degenerate_cuts"] == 0 or gold["discarded_sum"] < 1e-12:
-        assert abs(disc - gold["discarded_sum"]) <= 1e-8 * gold["discarded_sum"] + 1e-14
-        assert rel(e, gold["E"]) <= 1e-10
-        assert grad_ok(grad, np.array(gold["grad"]))
-    else:
-        assert abs(disc - gold["discarded_sum"]) <= 0.1 * gold["discarded_sum"]
-        assert abs(e - gold["E"]) <= 2.0 * np.abs(p.ham_c).sum() * np.sqrt(gold["discarded_sum"])
-    eb, gb, _ = plan.energy_grad_batched(np.stack([p.theta, p.theta]))
-    assert abs(eb[1] - e) <= 1e-13 * abs(e)
-    assert np.abs(gb[1] - grad).max() <= 1e-12 * np.abs(grad).max()
+    ref = np.array(gold["grad"])
+    print(f"instance {i}: {n} q, D={D}, eps={eps:g}, truncated gates {st['gates_truncated']}, discarded {disc:.3e}, "
+          f"degenerate cuts {fst['degenerate_cuts']}, E error {abs(e - gold['E']):.2e}, "
+          f"grad error {np.abs(grad - ref).max() / max(1.0, np.abs(ref).max()):.2e}")
+    assert fst["degenerate_cuts"] == 0
+    assert st["max_bond"] == max(gold["bonds"])
+    assert abs(disc - gold["discarded_sum"]) <= 1e-8 * gold["discarded_sum"] + 1e-14
+    assert rel(e, gold["E"]) <= 1e-10
+    assert grad_ok(grad, ref)
+    if i in (4, 3):
+        eb, gb, _ = plan.energy_grad_batched(np.stack([p.theta, p.theta]))
+        assert abs(eb[1] - e) <= 1e-13 * abs(e)
+        assert np.abs(gb[1] - grad).max() <= 1e-12 * np.abs(grad).max()
+    plan.free()
+
+
+def test_40_qubit_prefix_gradient_with_checkpoints_matches_oracle(ctx):
+    """Energy and gradient of the first 2000 gates of the 40-qubit D = 256
+    workload (capacity 256, 4-column Jacobi blocks) for every 100th Pauli
+    term, with the MPS checkpointed every 426 gates (8 compiled rotation
+    blocks on average) and each segment recomputed in the reverse pass."""
+    import dataclasses
+    from paper_2211_07983_amd import Plan
+    p, g = configs.load("c5")
+    gold = golden()["c5_prefix_grad"]
+    pre = Prefix(g, gold["gates"])
+    sub = slice(0, None, gold["term_stride"])
+    ps = dataclasses.replace(p, ham_x=p.ham_x[sub], ham_z=p.ham_z[sub], ham_c=p.ham_c[sub])
+    assert len(ps.ham_c) == gold["n_terms"] and gold["degenerate_cuts"] == 0
+    plan = Plan(ctx, p.occ, pre, p.n_qubits, ps.ham_x, ps.ham_z, ps.ham_c, p.c0, p.bond_dim, p.eps,
+                ckpt_gates=gold["ckpt_gates"])
+    th = np.array(p.theta[: plan.n_theta])
+    e, grad, st = plan.energy_grad(th)
+    ref = np.array(gold["grad"])
+    print(f"40 q prefix gradient: {plan.n_theta} parameters, E error {abs(e - gold['E']):.2e}, "
+          f"grad error {np.abs(grad - ref).max() / np.abs(ref).max():.2e}")
+    assert st["max_bond"] == max(gold["bonds"])
+    assert rel(e, gold["E"]) <= 1e-10
+    assert grad_ok(grad, ref)
     plan.free()

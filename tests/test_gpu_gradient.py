@@ -203,3 +203,48 @@ def test_gradient_validation_errors(ctx):
     with pytest.raises(MPSError) as ei:
         plan.energy_grad(p.theta[:-1])
     assert ei.value.code == -1
+
+
+def test_broadened_svd_adjoint_matches_oracle(ctx):
+    """C2 at eps = 1e-6 with the SVD adjoint's Lorentzian broadening (eta of
+    d / (d^2 + eta^2), d = s_j^2 - s_i^2): against the oracle with the same
+    eta, and visibly different from the unbroadened gradient, so a path that
+    ignored eta would fail."""
+    p, g = configs.load("c2", eps=configs.PAPER_EPS)
+    gold = golden()["c2_paper_broaden"]
+    plain = np.array(golden()["c2_paper"]["grad"])
+    ref = np.array(gold["grad"])
+    assert np.abs(ref - plain).max() > 1e-6 * np.abs(plain).max()
+    plan = make_plan(ctx, p, g, ckpt_gates=512, broaden=gold["broaden"])
+    e, grad, st = plan.energy_grad(p.theta)
+    print(f"broadened: grad error {np.abs(grad - ref).max() / np.abs(ref).max():.2e}, "
+          f"change from the plain gradient {np.abs(ref - plain).max() / np.abs(plain).max():.2e}")
+    assert rel(e, gold["E"]) <= 1e-10
+    assert grad_ok(grad, ref)
+    plan.free()
+
+
+def test_degenerate_cut_with_cotangent_is_reported(ctx):
+    """A truncation through an exactly degenerate pair that carries a
+    cotangent (the oracle raises there): strict_degenerate = 1 turns it into
+    MPS_EDEGEN; by default the pair is dropped and the gradient is finite;
+    so it is with broadening, whose Lorentzian is zero at d = 0."""
+    import degenerate_case as dc
+    from oracle import mps
+    from paper_2211_07983_amd import MPSError
+    p, g = dc.problem()
+    with pytest.raises(mps.SVDDegenerate):
+        mps.energy_grad(p, g, p.theta)
+    plan = make_plan(ctx, p, g, strict_degenerate=1)
+    with pytest.raises(MPSError, match="MPS_EDEGEN"):
+        plan.energy_grad(p.theta)
+    plan.free()
+    for kw in ({}, {"broaden": 1e-6}):
+        plan = make_plan(ctx, p, g, **kw)
+        e, grad, st = plan.energy_grad(p.theta)
+        assert st["degenerate_cuts"] == 1 and np.all(np.isfinite(grad))
+        plan.free()
+    # away from the degeneracy the strict plan evaluates
+    plan = make_plan(ctx, p, g, strict_degenerate=1)
+    plan.energy_grad(p.theta + 0.3)
+    plan.free()
