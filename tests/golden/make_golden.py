@@ -97,20 +97,21 @@ def batched_instance(i):
 # whose cuts never fall inside a degenerate pair (the oracle's degenerate-cut
 # count is zero), so E_D and g_D are unique; found by running the oracle over
 # the set's 12- and 16-qubit instances.
-C4_PARITY = (3, 8, 14, 17)
+C4_PARITY = (3, 5, 8, 14, 17)
 
 
-def batched_instance_paper(i):
-    """Instance i of the batched set at eps = 1e-6: energy, gradient, bonds,
+def batched_instance_paper(i, broaden=0.0):
+    """Instance i of the batched set at eps = 1e-6: energy, gradient (with the
+    SVD adjoint's Lorentzian broadening eta = broaden, 0 = none), bonds,
     discarded weight and the degenerate-cut count of the forward pass."""
     from vqe_inputs.compile import compile_problem
     from vqe_inputs.problem import make_problem
     n, ne, D, s1, s2 = configs.batched_instances()[i]
     p = make_problem(f"c4_{i}", n, ne, D, configs.PAPER_EPS, s1, s2, 0.05)
     g = compile_problem(p)
-    E, grad, info = mps.energy_grad(p, g, p.theta)
+    E, grad, info = mps.energy_grad(p, g, p.theta, broaden=broaden)
     _, finfo = mps.energy(p, g, p.theta)
-    return dict(n_qubits=n, D=D, eps=p.eps, E=E, grad=grad.tolist(), bonds=finfo["bonds"],
+    return dict(n_qubits=n, D=D, eps=p.eps, broaden=broaden, E=E, grad=grad.tolist(), bonds=finfo["bonds"],
                 discarded_sum=float(sum(finfo["discarded"])), degenerate_cuts=int(finfo["degenerate_cuts"]),
                 n_gates=int(g.n_gates))
 
@@ -170,6 +171,10 @@ ENTRIES = {"c1": lambda: exact_config("c1"), "c2": lambda: exact_config("c2"), "
            "c5_prefix_grad": c5_prefix_grad, "c2_paper_broaden": c2_paper_broaden,
            "alg1_c1_groups4": alg1_c1_groups4}
 ENTRIES.update({f"c4p_{i}": (lambda i=i: batched_instance_paper(i)) for i in C4_PARITY})
+# The same instances with the broadened SVD adjoint (eta = C2_BROADEN): where
+# nearly degenerate kept pairs carry cotangents the plain g_D is ill-conditioned
+# (eta = 1e-12 already moves it by 3e-6 on instance 8), the broadened one not.
+ENTRIES.update({f"c4p_{i}_b": (lambda i=i: batched_instance_paper(i, C2_BROADEN)) for i in (3, 8)})
 
 
 def main(names):
