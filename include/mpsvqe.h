@@ -166,6 +166,20 @@ mps_status mps_init_product(mps_ctx* ctx, int32_t n_qubits, const uint8_t* occ_b
 mps_status mps_apply_circuit(mps_state* st, const mps_circuit* circuit, const double* theta,
                              int32_t n_theta, mps_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation and results as mps_apply_circuit on the same state, bit for bit,
+ * with no device allocation of its own.  Its workspace is one fixed device
+ * array per GPU (about 2.7 MiB, held until the process ends): the gate
+ * workspace, theta, the statistics and the circuit, uploaded in chunks of
+ * 1024 gates.  Limits: the state's d_max <= 128 and n_theta <= 8192; larger
+ * requests give MPS_EINVAL before any work.  Every call on one GPU shares the
+ * array: calls that overlap on one GPU (other threads or streams) race.
+ * Arguments, ownership and the other errors as mps_apply_circuit; no
+ * timing (stats->t_gates_ms is 0).                                          */
+mps_status mps_apply_circuit_noalloc(mps_state* st, const mps_circuit* circuit, const double* theta,
+                                     int32_t n_theta, mps_stats* stats);
+
 /* Sec. 2 Eq. expect-val / Sec. 3 Eq. paulistringexp: energy = c0 +
  * sum_k coeff[k] <P_k> / <psi|psi> with a compensated final sum.
  * term_vals (nullable): host [n_terms] normalised <P_k> (real part).         */

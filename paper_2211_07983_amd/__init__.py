@@ -177,6 +177,16 @@ class State:
                                                        len(th), C.byref(s)))
         return s.as_dict()
 
+    def apply_circuit_noalloc(self, gates, theta):
+        """mps_apply_circuit_noalloc: the same update with the library's fixed
+        per-device workspace instead of device allocations."""
+        args = _CircuitArgs(gates)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        s = Stats()
+        self.ctx.check(self.ctx._lib.mps_apply_circuit_noalloc(self.h, C.byref(args.c), _ptr(th, C.c_double),
+                                                               len(th), C.byref(s)))
+        return s.as_dict()
+
     def expect(self, n_qubits, x, z, coeff, c0, terms=False):
         args = _PauliArgs(n_qubits, x, z, coeff, c0)
         e = C.c_double()

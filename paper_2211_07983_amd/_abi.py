@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_EDEVIC
 
 EXPORTS = [
     "mps_ctx_create", "mps_ctx_destroy", "mps_ctx_set_profiling", "mps_ctx_set_progress", "mps_last_error", "mps_init_product",
-    "mps_apply_circuit", "mps_expect_paulisum", "mps_plan_create", "mps_energy_grad",
+    "mps_apply_circuit", "mps_apply_circuit_noalloc", "mps_expect_paulisum", "mps_plan_create", "mps_energy_grad",
     "mps_energy_grad_batched", "mps_energy_grad_multi", "mps_plan_batch_width", "mps_energy_grad_psr",
     "mps_energy_grad_alg1",
     "mps_plan_energy", "mps_state_export", "mps_state_import", "mps_state_size", "mps_state_qubits",
@@ -94,6 +94,9 @@ def load(path=LIB_PATH):
     lib.mps_init_product.restype = C.c_int32
     lib.mps_apply_circuit.argtypes = [vp, C.POINTER(Circuit), C.POINTER(C.c_double), C.c_int32, C.POINTER(Stats)]
     lib.mps_apply_circuit.restype = C.c_int32
+    lib.mps_apply_circuit_noalloc.argtypes = [vp, C.POINTER(Circuit), C.POINTER(C.c_double), C.c_int32,
+                                              C.POINTER(Stats)]
+    lib.mps_apply_circuit_noalloc.restype = C.c_int32
     lib.mps_expect_paulisum.argtypes = [vp, C.POINTER(PauliSum), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.POINTER(Stats)]
     lib.mps_expect_paulisum.restype = C.c_int32

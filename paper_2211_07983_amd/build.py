@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmpsvqe.so")
-SOURCES = ["gate.hip", "sweep.hip", "sweep32.hip", "adjoint.hip", "alg1.hip", "engine.hip", "plan.hip"]
+SOURCES = ["gate.hip", "sweep.hip", "sweep32.hip", "adjoint.hip", "alg1.hip", "engine.hip", "plan.hip",
+           "noalloc.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -448,6 +448,7 @@ mps_status mps_ctx_create(int32_t device, void* hip_stream, mps_ctx** out) {
   int coop = 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop)
     return MPS_EDEVICE;
+  noalloc_device_init(device);
   mps_ctx* c = new mps_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;

@@ -41,6 +41,8 @@ void run_gates(mps_state* st, DevCircuit& C, const double* theta_dev, int g0, in
 void read_stats(mps_ctx* ctx, mps_stats* out, int64_t gates);
 void validate_circuit(const mps_circuit* c, int N, int n_theta);
 void validate_theta(const double* theta, int n_theta);
+// Sets up the allocation-free workspace of `device` (current), once per device.
+void noalloc_device_init(int device);
 
 mps_state* plan_new_state(mps_ctx* ctx, int N, const mps_trunc& tr, const uint8_t* occ);
 void plan_forward_energy(mps_plan* p, const double* theta, int n_theta, int on_device, double* energy,
