@@ -255,6 +255,28 @@ mps_status mps_energy_grad_alg1(mps_plan* plan, const double* theta, int32_t n_t
 mps_status mps_energy_grad_multi(mps_plan* const* plans, int32_t n_plans, const double* thetas, int32_t n_theta,
                                  double* energies, double* grads, mps_stats* stats);
 
+/* Energies and gradients of independent problem instances of any size in
+ * shared launches (the batched-instance workload: instances that differ in
+ * qubit count, circuit, Hamiltonian, d_max, eps, precision and checkpoint
+ * interval; Sec. 5 runs many molecules through one ansatz family).  Each
+ * plan is one lane of the same cooperative gate-chain launches: every lane
+ * carries its own circuit, capacity, Jacobi block width and work-group
+ * count, and a launch advances every lane by one of its own checkpoint
+ * segments (lanes whose circuits are shorter finish early).  Energies and
+ * sweep adjoints then run per plan, and the reverse pass recomputes the
+ * lanes' segments in shared launches and runs the gate adjoints of all lanes
+ * step by step in shared launch sets.  Larger sets run in groups that one
+ * launch holds.  plans[n_plans]: distinct plans of one context;
+ * thetas[i]: host array of plan i's n_theta parameters; energies: host
+ * [n_plans]; grads[i]: host array of plan i's n_theta.  Results equal each
+ * plan's mps_energy_grad up to rounding.  stats (nullable): sums and maxima
+ * over the instances, the wall time in t_backward_ms.  NULL, repeated or
+ * non-finite arguments, or plans of different contexts: MPS_EINVAL before
+ * any work; the other errors as mps_energy_grad (MPS_EDEGEN when any plan
+ * asks for strict_degenerate).                                             */
+mps_status mps_energy_grad_plans(mps_plan* const* plans, int32_t n_plans, const double* const* thetas,
+                                 double* energies, double* const* grads, mps_stats* stats);
+
 /* Parameter vectors that one batched launch holds for this plan (the SVD of
  * each vector occupies ceil(2 d_max / (2 W)) compute units); larger batches
  * run in groups of this size.  Returns <= 0 on error.                      */

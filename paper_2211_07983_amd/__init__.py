@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 from ._abi import GradOpts, PauliSum, Stats, Trunc
 
-__all__ = ["MPSError", "Context", "State", "Plan", "EnergyGrad", "energy_grad_multi", "lib"]
+__all__ = ["MPSError", "Context", "State", "Plan", "EnergyGrad", "energy_grad_multi", "energy_grad_plans", "lib"]
 
 
 def lib():
@@ -365,6 +365,27 @@ def energy_grad_multi(plans, thetas):
     ctx.check(ctx._lib.mps_energy_grad_multi(hs, len(plans), th.ctypes.data_as(C.c_void_p), th.shape[1],
                                              _ptr(e, C.c_double), g.ctypes.data_as(C.c_void_p), C.byref(s)))
     return e, g, s.as_dict()
+
+
+def energy_grad_plans(plans, thetas):
+    """Energies and gradients of independent instances of any size (each plan
+    its own circuit, qubit count, d_max and Hamiltonian) as lanes of shared
+    gate-chain launches (mps_energy_grad_plans).  plans: distinct Plans of one
+    context; thetas: one parameter array per plan.  Returns (energies
+    [n_plans], [grad per plan], stats)."""
+    plans = list(plans)
+    if not plans or len(thetas) != len(plans):
+        raise ValueError("one theta array per plan")
+    ctx = plans[0].ctx
+    ths = [np.ascontiguousarray(t, dtype=np.float64) for t in thetas]
+    gs = [np.zeros(max(1, len(t))) for t in ths]
+    hs = (C.c_void_p * len(plans))(*[p.h for p in plans])
+    tp = (C.c_void_p * len(plans))(*[t.ctypes.data if len(t) else None for t in ths])
+    gp = (C.c_void_p * len(plans))(*[g.ctypes.data for g in gs])
+    e = np.zeros(len(plans))
+    s = Stats()
+    ctx.check(ctx._lib.mps_energy_grad_plans(hs, len(plans), tp, _ptr(e, C.c_double), gp, C.byref(s)))
+    return e, [g[:len(t)] for g, t in zip(gs, ths)], s.as_dict()
 
 
 def _energy_grad_function():

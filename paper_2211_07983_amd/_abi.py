@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ENOMEM", -3: "MPS_EDEVIC
 EXPORTS = [
     "mps_ctx_create", "mps_ctx_destroy", "mps_ctx_set_profiling", "mps_ctx_set_progress", "mps_last_error", "mps_init_product",
     "mps_apply_circuit", "mps_apply_circuit_noalloc", "mps_expect_paulisum", "mps_plan_create", "mps_energy_grad",
-    "mps_energy_grad_batched", "mps_energy_grad_multi", "mps_plan_batch_width", "mps_energy_grad_psr",
+    "mps_energy_grad_batched", "mps_energy_grad_multi", "mps_energy_grad_plans", "mps_plan_batch_width", "mps_energy_grad_psr",
     "mps_energy_grad_alg1",
     "mps_plan_energy", "mps_state_export", "mps_state_import", "mps_state_size", "mps_state_qubits",
     "mps_state_free", "mps_plan_free",
@@ -112,6 +112,9 @@ def load(path=LIB_PATH):
     lib.mps_energy_grad_multi.argtypes = [C.POINTER(vp), C.c_int32, vp, C.c_int32, C.POINTER(C.c_double), vp,
                                           C.POINTER(Stats)]
     lib.mps_energy_grad_multi.restype = C.c_int32
+    lib.mps_energy_grad_plans.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp), C.POINTER(C.c_double),
+                                          C.POINTER(vp), C.POINTER(Stats)]
+    lib.mps_energy_grad_plans.restype = C.c_int32
     lib.mps_energy_grad_alg1.argtypes = [vp, vp, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp, vp,
                                          C.POINTER(Stats)]
     lib.mps_energy_grad_alg1.restype = C.c_int32

@@ -240,11 +240,17 @@ struct AdjLane {
   double* lb_in;      // lambar_{n-1} (accumulated)
   double* gphi;       // [G] dE/dphi of this evaluation
   const double* theta;
+  GateTable gt;       // the lane's circuit
+  int g;              // gate index in gt
+  int kind;           // 1: PARAM gate (dE/dphi is written)
+  int dc, ldc, ldv;   // bond capacity and leading dimensions of the tape's C, A and V
+  double eta;         // Lorentzian broadening of the SVD adjoint (0: none)
 };
 
 // A1: Wbar[mu, c] = sum_row conj(Bbar_n[row, mu]) / nu * C[row, c] + Bbar_{n+1}[mu, c]
-__global__ __launch_bounds__(256) void k_adj_wbar(const AdjLane* AL, int dc, int ldc) {
+__global__ __launch_bounds__(256) void k_adj_wbar(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int dc = ln.dc, ldc = ln.ldc;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -271,8 +277,9 @@ __global__ __launch_bounds__(256) void k_adj_wbar(const AdjLane* AL, int dc, int
 }
 
 // A2: nu_bar and s_bar of the kept values (one block)
-__global__ __launch_bounds__(256) void k_adj_scalars(const AdjLane* AL, int dc, int ldv) {
+__global__ __launch_bounds__(256) void k_adj_scalars(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int dc = ln.dc, ldv = ln.ldv;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -298,8 +305,9 @@ __global__ __launch_bounds__(256) void k_adj_scalars(const AdjLane* AL, int dc, 
 }
 
 // A3: Kt[i, mu] = sum_c conj(P[c, i]) conj(Wbar[mu, c]),  P = V[:, perm]
-__global__ __launch_bounds__(256) void k_adj_K(const AdjLane* AL, int dc, int ldv) {
+__global__ __launch_bounds__(256) void k_adj_K(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int dc = ln.dc, ldv = ln.ldv;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -319,8 +327,9 @@ __global__ __launch_bounds__(256) void k_adj_K(const AdjLane* AL, int dc, int ld
 }
 
 // A4: kscale = max |Kt| (one block, deterministic)
-__global__ __launch_bounds__(256) void k_adj_kscale(const AdjLane* AL, int dc) {
+__global__ __launch_bounds__(256) void k_adj_kscale(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int dc = ln.dc;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
   __shared__ double red[256];
@@ -340,8 +349,10 @@ __global__ __launch_bounds__(256) void k_adj_kscale(const AdjLane* AL, int dc) {
 }
 
 // A5: Phi (sorted basis), Gamma_ij / s_i of the complex SVD adjoint
-__global__ void k_adj_phi(const AdjLane* AL, int dc, double eta, GateStats* st) {
+__global__ void k_adj_phi(const AdjLane* AL, GateStats* st) {
   const AdjLane& ln = AL[blockIdx.z];
+  const double eta = ln.eta;
+  const int dc = ln.dc;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -375,8 +386,9 @@ __global__ void k_adj_phi(const AdjLane* AL, int dc, double eta, GateStats* st) 
 }
 
 // A6: T[row, j] = sum_i A[row, perm i] Phi[i, j]
-__global__ __launch_bounds__(256) void k_adj_T(const AdjLane* AL, int ldc) {
+__global__ __launch_bounds__(256) void k_adj_T(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int ldc = ln.ldc;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -394,8 +406,9 @@ __global__ __launch_bounds__(256) void k_adj_T(const AdjLane* AL, int ldc) {
 }
 
 // A7: Mbar[row, c] = sum_j T[row, j] conj(P[c, j])
-__global__ __launch_bounds__(256) void k_adj_Mbar(const AdjLane* AL, int ldv) {
+__global__ __launch_bounds__(256) void k_adj_Mbar(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int ldv = ln.ldv;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -413,8 +426,9 @@ __global__ __launch_bounds__(256) void k_adj_Mbar(const AdjLane* AL, int ldv) {
 }
 
 // A8: Cbar[row, c] = sum_mu Bbar_n[row, mu]/nu conj(P[c, mu]) + lambda_in[alpha] Mbar[row, c]
-__global__ __launch_bounds__(256) void k_adj_Cbar(const AdjLane* AL, int dc, int ldv) {
+__global__ __launch_bounds__(256) void k_adj_Cbar(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int dc = ln.dc, ldv = ln.ldv;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -441,8 +455,9 @@ __global__ __launch_bounds__(256) void k_adj_Cbar(const AdjLane* AL, int dc, int
 }
 
 // A9: lambar_{n-1}[alpha] += Re sum conj(Mbar[(alpha,i'), c]) C[(alpha,i'), c]
-__global__ __launch_bounds__(256) void k_adj_lambar(const AdjLane* AL, int ldc) {
+__global__ __launch_bounds__(256) void k_adj_lambar(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int ldc = ln.ldc;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -463,8 +478,10 @@ __global__ __launch_bounds__(256) void k_adj_lambar(const AdjLane* AL, int ldc) 
 }
 
 // A10: Theta_bar = Q^dagger C_bar on (i', j'); dphi partial sums Re <C_bar, D C>
-__global__ __launch_bounds__(256) void k_adj_theta(const AdjLane* AL, GateTable gt, int g, int ldc) {
+__global__ __launch_bounds__(256) void k_adj_theta(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const GateTable& gt = ln.gt;
+  const int g = ln.g, ldc = ln.ldc;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -516,8 +533,9 @@ __global__ __launch_bounds__(256) void k_adj_theta(const AdjLane* AL, GateTable 
 }
 
 // A11: Bbar_n[(alpha,i), gamma] = sum_c Theta_bar[(alpha,i), c] conj(B_{n+1}[gamma, c])
-__global__ __launch_bounds__(256) void k_adj_Bl(const AdjLane* AL, int dc) {
+__global__ __launch_bounds__(256) void k_adj_Bl(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int dc = ln.dc;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -541,8 +559,9 @@ __global__ __launch_bounds__(256) void k_adj_Bl(const AdjLane* AL, int dc) {
 }
 
 // A12: Bbar_{n+1}[gamma, c] = sum_row conj(B_n[row, gamma]) Theta_bar[row, c]
-__global__ __launch_bounds__(256) void k_adj_Br(const AdjLane* AL, int dc) {
+__global__ __launch_bounds__(256) void k_adj_Br(const AdjLane* AL) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int dc = ln.dc;
   const GateRec& R = ln.R;
   const AdjWork& W = ln.W;
   const GateDims& d = ln.d;
@@ -566,8 +585,9 @@ __global__ __launch_bounds__(256) void k_adj_Br(const AdjLane* AL, int dc) {
 }
 
 // A13: lambar_n = 0 (the old lambda_n was overwritten by this gate); dE/dphi
-__global__ void k_adj_finish(const AdjLane* AL, int dc, int nparts, int g, int param) {
+__global__ void k_adj_finish(const AdjLane* AL, int nparts) {
   const AdjLane& ln = AL[blockIdx.z];
+  const int dc = ln.dc, g = ln.g, param = ln.kind;
   const AdjWork& W = ln.W;
   double* lbar_out = ln.lb_out;
   double* gphi = ln.gphi;
@@ -626,11 +646,13 @@ struct SweepAdjPlan {
 };
 
 struct BatchSet;
+struct MixSet;
 struct PlanAdj {
   SweepAdjPlan sw;
   DevBuf chain_start, chain_list;
   bool chain_built = false;
   BatchSet* batch = nullptr;   // lanes of the batched form (allocated on first use)
+  MixSet* mix = nullptr;       // lanes of mixed-instance calls led by this plan
   ~PlanAdj();
 };
 
@@ -1070,23 +1092,22 @@ static size_t adjwork_layout(int ncap, int dc, AdjWork* W, char* w) {
 
 // The adjoint of one gate (A1..A13) for nl lanes; mx holds the largest sizes
 // over the lanes, which set the grids.
-static void launch_gate_adjoint(const AdjLane* al, int nl, const GateDims& mx, int g, int param_kind,
-                                const GateTable& gt, int dc, const GateWork& gw, double eta, hipStream_t s) {
+static void launch_gate_adjoint(const AdjLane* al, int nl, const GateDims& mx, GateStats* stats, hipStream_t s) {
   const int M = 2 * mx.a, nb = 2 * mx.b;
-  hipLaunchKernelGGL(k_adj_wbar, gemm_grid(mx.r, nb, nl), dim3(256), 0, s, al, dc, gw.ldc);
-  hipLaunchKernelGGL(k_adj_scalars, dim3(1, 1, nl), dim3(256), 0, s, al, dc, gw.ldv);
-  hipLaunchKernelGGL(k_adj_K, gemm_grid(nb, mx.r, nl), dim3(256), 0, s, al, dc, gw.ldv);
-  hipLaunchKernelGGL(k_adj_kscale, dim3(1, 1, nl), dim3(256), 0, s, al, dc);
-  hipLaunchKernelGGL(k_adj_phi, dim3((nb * nb + 255) / 256, 1, nl), dim3(256), 0, s, al, dc, eta, gw.stats);
-  hipLaunchKernelGGL(k_adj_T, gemm_grid(M, nb, nl), dim3(256), 0, s, al, gw.ldc);
-  hipLaunchKernelGGL(k_adj_Mbar, gemm_grid(M, nb, nl), dim3(256), 0, s, al, gw.ldv);
-  hipLaunchKernelGGL(k_adj_Cbar, gemm_grid(M, nb, nl), dim3(256), 0, s, al, dc, gw.ldv);
-  hipLaunchKernelGGL(k_adj_lambar, dim3(mx.a, 1, nl), dim3(256), 0, s, al, gw.ldc);
+  hipLaunchKernelGGL(k_adj_wbar, gemm_grid(mx.r, nb, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_scalars, dim3(1, 1, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_K, gemm_grid(nb, mx.r, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_kscale, dim3(1, 1, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_phi, dim3((nb * nb + 255) / 256, 1, nl), dim3(256), 0, s, al, stats);
+  hipLaunchKernelGGL(k_adj_T, gemm_grid(M, nb, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_Mbar, gemm_grid(M, nb, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_Cbar, gemm_grid(M, nb, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_lambar, dim3(mx.a, 1, nl), dim3(256), 0, s, al);
   const int nparts = (mx.a * mx.b + 255) / 256;
-  hipLaunchKernelGGL(k_adj_theta, dim3(nparts, 1, nl), dim3(256), 0, s, al, gt, g, gw.ldc);
-  hipLaunchKernelGGL(k_adj_Bl, gemm_grid(M, mx.m, nl), dim3(256), 0, s, al, dc);
-  hipLaunchKernelGGL(k_adj_Br, gemm_grid(mx.m, nb, nl), dim3(256), 0, s, al, dc);
-  hipLaunchKernelGGL(k_adj_finish, dim3(1, 1, nl), dim3(256), 0, s, al, dc, nparts, g, param_kind);
+  hipLaunchKernelGGL(k_adj_theta, dim3(nparts, 1, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_Bl, gemm_grid(M, mx.m, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_Br, gemm_grid(mx.m, nb, nl), dim3(256), 0, s, al);
+  hipLaunchKernelGGL(k_adj_finish, dim3(1, 1, nl), dim3(256), 0, s, al, nparts);
 }
 
 // Sizes of a recorded gate (from the tape's meta fields read back to the host).
@@ -1163,6 +1184,8 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
   std::vector<int> meta((size_t)nlanes * K * 16);
   std::vector<double> dmeta((size_t)nlanes * K * 16);
   std::vector<AdjLane> rec;      // lives until the final synchronisation below
+  // the adjoint records of the largest batch, allocated once for the pass
+  p->adjl_dev.ensure((size_t)nlanes * K * sizeof(AdjLane));
   std::vector<GateDims> dd;
   for (int hi = p->n_seg - 1; hi >= 0; hi -= nlanes) {
     const int lo = std::max(0, hi - nlanes + 1), nl = hi - lo + 1;
@@ -1217,6 +1240,13 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
         a1.lb_in = lambar + (size_t)n * dc;
         a1.gphi = gphi;
         a1.theta = th;
+        a1.gt = p->C.tab;
+        a1.g = g;
+        a1.kind = p->C.kind_h[g];
+        a1.dc = dc;
+        a1.ldc = gw.ldc;
+        a1.ldv = gw.ldv;
+        a1.eta = p->opts.broaden;
         rec.push_back(a1);
         dd.push_back(a1.d);
       }
@@ -1227,7 +1257,7 @@ void plan_backward(mps_plan* p, double* grad, int on_device, mps_stats* stats) {
     for (int l = nl - 1; l >= 0; --l) {
       const GateLane& ln = p->lanes_h[l];
       for (int g = ln.g0 + ln.ng - 1; g >= ln.g0; --g, ++k)
-        launch_gate_adjoint(rec_d + k, 1, dd[k], g, p->C.kind_h[g], p->C.tab, dc, gw, p->opts.broaden, s);
+        launch_gate_adjoint(rec_d + k, 1, dd[k], gw.stats, s);
       HIPCHK(hipGetLastError());
       if (ctx->progress) {
         HIPCHK(hipStreamSynchronize(s));
@@ -1475,6 +1505,13 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
         a1.lb_in = lambar + (size_t)n * dc;
         a1.gphi = (double*)bl->gphi.p;
         a1.theta = lh[l].theta;
+        a1.gt = p->C.tab;
+        a1.g = g;
+        a1.kind = p->C.kind_h[g];
+        a1.dc = dc;
+        a1.ldc = gw.ldc;
+        a1.ldv = gw.ldv;
+        a1.eta = p->opts.broaden;
         rec.push_back(a1);
         m.a = std::max(m.a, a1.d.a);
         m.m = std::max(m.m, a1.d.m);
@@ -1487,7 +1524,7 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
     HIPCHK(hipMemcpyAsync(rec_d, rec.data(), rec.size() * sizeof(AdjLane), hipMemcpyHostToDevice, s));
     size_t k = 0;
     for (int g = g0 + ng - 1; g >= g0; --g, ++k)
-      launch_gate_adjoint(rec_d + k * nl, nl, mx[k], g, p->C.kind_h[g], p->C.tab, dc, gw, p->opts.broaden, s);
+      launch_gate_adjoint(rec_d + k * nl, nl, mx[k], gw.stats, s);
     HIPCHK(hipGetLastError());
     if (ctx->progress) {
       HIPCHK(hipStreamSynchronize(s));
@@ -1780,4 +1817,464 @@ void plan_energy_grad_psr(mps_plan* p, const double* theta, int n_theta, double*
   }
 }
 
-PlanAdj::~PlanAdj() { delete batch; }
+// ============================================================================
+// Mixed instances: plans with their own circuits, qubit counts, bond
+// capacities, Hamiltonians, truncations and checkpoint intervals as lanes of
+// the same cooperative launches (k_chain_mixed).  Lanes of one launch take
+// their work-groups from the same XCD where the counts allow; each launch
+// advances every lane by one of its own checkpoint segments, so lanes with
+// shorter circuits finish early and idle.  Energies and sweep adjoints then
+// run per lane with its own plan, and the reverse pass walks the segment
+// index down: lanes recompute their segment (all in one launch), then the
+// gate adjoints of all lanes run step by step in shared launch sets, each
+// lane record carrying its own gate, capacity and leading dimensions.
+// ============================================================================
+struct MixLaneBufs {
+  mps_state* st = nullptr;
+  mps_state* rp = nullptr;
+  DevBuf ckpt, Bbar, lambar, gphi, grad, work, tape;
+  ~MixLaneBufs() {
+    delete st;
+    delete rp;
+  }
+};
+
+struct MixSet {
+  std::vector<MixLaneBufs*> lanes;
+  DevBuf thetas, aux, lanes_dev, blk_dev, adj_dev;
+  ~MixSet() {
+    for (MixLaneBufs* l : lanes) delete l;
+  }
+};
+
+// Per-lane constants of a mixed launch.
+struct MixInfo {
+  mps_plan* p;
+  int dc, W, P, ncap, ldc, ldv, K, G, n_seg;
+  TapeLayout L;
+  size_t ck_B, ck_dims, ck_lam, ck_lamoff, ck_stride;
+  double tol;
+};
+
+static MixInfo mix_info(mps_plan* p) {
+  MixInfo m;
+  m.p = p;
+  m.dc = p->state->dcap;
+  m.W = svd_width(m.dc);
+  m.P = (2 * m.dc + 2 * m.W - 1) / (2 * m.W);
+  m.ncap = 2 * m.P * m.W;
+  m.ldc = 2 * m.dc;
+  m.ldv = m.ncap;
+  m.K = std::max(1, p->opts.ckpt_gates);
+  m.G = p->C.G;
+  m.n_seg = std::max(1, (m.G + m.K - 1) / m.K);
+  m.L = tape_layout(m.dc, m.ncap, m.ldc, m.ldv);
+  m.ck_B = p->state->B.bytes;
+  m.ck_dims = p->state->dims.bytes;
+  m.ck_lam = p->state->lam.bytes;
+  m.ck_lamoff = ((m.ck_B + m.ck_dims + 7) / 8) * 8;
+  m.ck_stride = ((m.ck_lamoff + m.ck_lam + 255) / 256) * 256;
+  m.tol = std::max(1e-15, 8.0 * std::sqrt((double)m.ldc) * 2.220446049250313e-16);
+  return m;
+}
+
+// Work-group table of a mixed launch: lanes go to the XCD with the fewest
+// work-groups so far (work-group i runs on XCD i % 8), and the work-groups of
+// XCD x are blocks x, x + 8, x + 16, ...  Returns the block count.
+static int mix_block_table(const std::vector<MixInfo>& info, const std::vector<int>& lanes, std::vector<int2>& blk) {
+  const int X = 8;
+  std::vector<std::vector<int2>> per(X);
+  for (int l : lanes) {
+    int x = 0;
+    for (int y = 1; y < X; ++y)
+      if (per[y].size() < per[x].size()) x = y;
+    for (int q = 0; q < info[l].P; ++q) per[x].push_back(make_int2(l, q));
+  }
+  size_t depth = 0;
+  for (auto& v : per) depth = std::max(depth, v.size());
+  blk.assign(depth * X, make_int2(-1, 0));
+  for (int x = 0; x < X; ++x)
+    for (size_t k = 0; k < per[x].size(); ++k) blk[k * X + x] = per[x][k];
+  return (int)blk.size();
+}
+
+static void mixed_group(mps_plan* lead, const std::vector<MixInfo>& info, const std::vector<int>& grp,
+                        const std::vector<const double*>& th_dev, double* energies, std::vector<double*>& grad_dev,
+                        GateStats* gsum) {
+  mps_ctx* ctx = lead->ctx;
+  hipStream_t s = ctx->stream;
+  PlanAdj& LA = adj_of(lead);
+  if (!LA.mix) LA.mix = new MixSet();
+  MixSet& S = *LA.mix;
+  const int nl = (int)grp.size();
+  while ((int)S.lanes.size() < nl) S.lanes.push_back(new MixLaneBufs());
+  size_t shm = 0;
+  int max_dc = 2;
+  for (int l : grp) {
+    shm = std::max(shm, chain_lds_bytes(info[l].dc));
+    max_dc = std::max(max_dc, info[l].dc);
+  }
+  // the shared Jacobi block schedules and the context's statistics block
+  ctx->ensure_gate_work(max_dc, lead->trunc, lead->opts.max_sweeps);
+  const GateWork gw = ctx->gw;
+  const size_t aux_lane = 128 * sizeof(int) + 256 * sizeof(double) + sizeof(GateStats) + 64;
+  char* aux = (char*)S.aux.ensure((size_t)nl * aux_lane + 64 + (size_t)nl * 8);
+  int* lane_err = (int*)(aux + (size_t)nl * aux_lane);
+  unsigned long long* bars = (unsigned long long*)(aux + (size_t)nl * aux_lane + 64);
+  HIPCHK(hipMemsetAsync(aux, 0, (size_t)nl * aux_lane + 64 + (size_t)nl * 8, s));
+  std::vector<MixLane> lh(nl);
+  std::vector<AdjWork> W(nl);
+  int S_max = 0;
+  for (int j = 0; j < nl; ++j) {
+    const MixInfo& m = info[grp[j]];
+    mps_plan* p = m.p;
+    MixLaneBufs* b = S.lanes[j];
+    const int N = p->N;
+    if (!b->st || b->st->N != N || b->st->dcap != m.dc || b->st->trunc.eps != p->trunc.eps ||
+        b->st->trunc.d_max != p->trunc.d_max || b->st->trunc.precision != p->trunc.precision) {
+      delete b->st;
+      delete b->rp;
+      b->st = nullptr;
+      b->rp = nullptr;
+      b->st = plan_new_state(ctx, N, p->trunc, nullptr);
+      b->rp = plan_new_state(ctx, N, p->trunc, nullptr);
+    }
+    const size_t site = (size_t)m.dc * 2 * m.dc;
+    b->ckpt.ensure((size_t)m.n_seg * m.ck_stride);
+    b->Bbar.ensure((size_t)N * site * sizeof(zd));
+    b->lambar.ensure((size_t)(N + 1) * m.dc * sizeof(double));
+    b->gphi.ensure((size_t)std::max(1, m.G) * sizeof(double));
+    b->tape.ensure((size_t)m.K * m.L.rec);
+    adjwork_layout(m.ncap, m.dc, &W[j], (char*)b->work.ensure(adjwork_layout(m.ncap, m.dc, nullptr, nullptr)));
+    HIPCHK(hipMemsetAsync(b->lambar.p, 0, b->lambar.bytes, s));
+    HIPCHK(hipMemsetAsync(b->gphi.p, 0, b->gphi.bytes, s));
+    MixLane& ml = lh[j];
+    std::memset(&ml, 0, sizeof(ml));
+    char* la = aux + (size_t)j * aux_lane;
+    ml.ln.rotflag = (int*)la;
+    ml.ln.nrm_part = (double*)(la + 128 * sizeof(int));
+    ml.ln.stats = (GateStats*)(la + 128 * sizeof(int) + 256 * sizeof(double));
+    ml.ln.bar = bars + j;
+    ml.ln.err = lane_err;
+    ml.ln.theta = th_dev[grp[j]];
+    ml.ln.shift_gate = -1;
+    ml.ln.shift = 0.0;
+    ml.ln.tape = (char*)b->tape.p;
+    LaneConst& c = ml.c;
+    c.sched = gw.sched;
+    c.gt = p->C.tab;
+    c.L = m.L;
+    c.ldc = m.ldc;
+    c.ldv = m.ldv;
+    c.ncap = m.ncap;
+    c.dmax = p->trunc.d_max;
+    c.max_sweeps = std::min(std::max(p->opts.max_sweeps, 1), 100);
+    c.nparts = ((2 * m.dc + ZT_M - 1) / ZT_M) * ((2 * m.dc + ZT_M - 1) / ZT_M);
+    c.eps = p->trunc.eps;
+    c.tol = m.tol;
+    c.ck_B = m.ck_B;
+    c.ck_dims = m.ck_dims;
+    c.ck_lam = m.ck_lam;
+    ml.W = m.W;
+    ml.nblk = m.P;
+    S_max = std::max(S_max, m.n_seg);
+    init_product(b->st, (const uint8_t*)p->state->occ.p);
+  }
+  std::vector<int> all(nl);
+  for (int j = 0; j < nl; ++j) all[j] = j;
+  std::vector<MixInfo> linfo(nl);
+  for (int j = 0; j < nl; ++j) linfo[j] = info[grp[j]];
+  std::vector<int2> blk;
+  const int T = mix_block_table(linfo, all, blk);
+  const int2* blk_d = upload(S.blk_dev, blk.data(), blk.size(), s);
+  MixLane* lanes_d = (MixLane*)S.lanes_dev.ensure((size_t)nl * sizeof(MixLane));
+  auto launch = [&]() {
+    HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(MixLane), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(bars, 0, (size_t)nl * sizeof(unsigned long long), s));
+    HIPCHK(launch_chain_mixed(lanes_d, blk_d, T, shm, s));
+    // the host lane table is rewritten only after this launch has read it
+    HIPCHK(hipStreamSynchronize(s));
+    int err = 0;
+    HIPCHK(hipMemcpy(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) fail(MPS_EDEVICE, "a lane barrier of the mixed gate chain timed out");
+  };
+  // ---- forward: segment sg of every lane that has one; a lane's last
+  // segment records its tape
+  for (int sg = 0; sg < S_max; ++sg) {
+    for (int j = 0; j < nl; ++j) {
+      const MixInfo& m = linfo[j];
+      MixLane& ml = lh[j];
+      ml.ln.st = view_of(S.lanes[j]->st);
+      if (sg < m.n_seg) {
+        ml.ln.g0 = sg * m.K;
+        ml.ln.ng = std::min(m.G, (sg + 1) * m.K) - sg * m.K;
+        ml.record = sg == m.n_seg - 1;
+        ml.ln.rec_stride = ml.record ? 1 : 0;
+        ml.ln.ckpt = (char*)S.lanes[j]->ckpt.p + (size_t)sg * m.ck_stride;
+      } else {
+        ml.ln.g0 = 0;
+        ml.ln.ng = 0;
+        ml.record = 0;
+        ml.ln.ckpt = nullptr;
+      }
+    }
+    launch();
+    if (ctx->progress) ctx->progress(ctx->progress_user, "forward", sg + 1, S_max);
+  }
+  // ---- statistics of the forward pass
+  std::vector<GateStats> st(nl);
+  for (int j = 0; j < nl; ++j)
+    HIPCHK(hipMemcpyAsync(&st[j], lh[j].ln.stats, sizeof(GateStats), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int j = 0; j < nl; ++j) HIPCHK(hipMemsetAsync(lh[j].ln.stats, 0, sizeof(GateStats), s));
+  // ---- energies and sweep adjoints, lane by lane with each lane's plan
+  for (int j = 0; j < nl; ++j) {
+    mps_plan* p = linfo[j].p;
+    MixLaneBufs* b = S.lanes[j];
+    std::vector<int> dims(p->N + 1);
+    run_energy(b->st, p->H);
+    double ev[3];
+    HIPCHK(hipMemcpyAsync(ev, ctx->sb.energy, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(dims.data(), b->st->dims.p, (p->N + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    energies[grp[j]] = ev[0];
+    run_sweep_adjoint(p, dims, b->st, (zd*)b->Bbar.p, ev[0], ev[2]);
+  }
+  // ---- reverse pass: segment index down; every lane with such a segment
+  // recomputes it (a lane's last one was recorded by the forward pass)
+  std::vector<AdjLane> rec;
+  for (int sg = S_max - 1; sg >= 0; --sg) {
+    bool any_recompute = false;
+    for (int j = 0; j < nl; ++j) {
+      const MixInfo& m = linfo[j];
+      MixLane& ml = lh[j];
+      MixLaneBufs* b = S.lanes[j];
+      ml.ln.ckpt = nullptr;
+      if (sg < m.n_seg - 1) {
+        const char* base = (const char*)b->ckpt.p + (size_t)sg * m.ck_stride;
+        HIPCHK(hipMemcpyAsync(b->rp->B.p, base, m.ck_B, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(b->rp->dims.p, base + m.ck_B, m.ck_dims, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(b->rp->lam.p, base + m.ck_lamoff, m.ck_lam, hipMemcpyDeviceToDevice, s));
+        ml.ln.st = view_of(b->rp);
+        ml.ln.g0 = sg * m.K;
+        ml.ln.ng = std::min(m.G, (sg + 1) * m.K) - sg * m.K;
+        ml.ln.rec_stride = 1;
+        ml.record = 1;
+        any_recompute = true;
+      } else {
+        ml.ln.ng = 0;   // no segment, or recorded by the forward pass
+        ml.record = 0;
+      }
+    }
+    if (any_recompute) launch();
+    // gate sizes of every lane's segment, read back from the tape records
+    std::vector<int> ng(nl, 0), g0(nl, 0);
+    std::vector<std::vector<int>> meta(nl);
+    std::vector<std::vector<double>> dmeta(nl);
+    for (int j = 0; j < nl; ++j) {
+      const MixInfo& m = linfo[j];
+      if (sg >= m.n_seg) continue;
+      g0[j] = sg * m.K;
+      ng[j] = std::min(m.G, (sg + 1) * m.K) - g0[j];
+      meta[j].resize((size_t)ng[j] * 16);
+      dmeta[j].resize((size_t)ng[j] * 16);
+      const char* tb = (const char*)S.lanes[j]->tape.p;
+      HIPCHK(hipMemcpy2DAsync(meta[j].data(), 16 * sizeof(int), tb + m.L.ometa, m.L.rec, 16 * sizeof(int), ng[j],
+                              hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpy2DAsync(dmeta[j].data(), 16 * sizeof(double), tb + m.L.odmeta, m.L.rec, 16 * sizeof(double),
+                              ng[j], hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    // lanes in order of decreasing segment length, so that the lanes still
+    // active at step k are a prefix of each step's records
+    std::vector<int> order;
+    for (int j = 0; j < nl; ++j)
+      if (ng[j] > 0) order.push_back(j);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ng[x] > ng[y]; });
+    if (order.empty()) continue;
+    const int steps = ng[order[0]];
+    rec.clear();
+    std::vector<std::pair<int, GateDims>> step_launch;   // (active lanes, largest sizes)
+    for (int k = 0; k < steps; ++k) {
+      GateDims mx{0, 0, 0, 0, 0, 0.0};
+      int act = 0;
+      for (int j : order) {
+        if (k >= ng[j]) break;
+        const MixInfo& m = linfo[j];
+        mps_plan* p = m.p;
+        MixLaneBufs* b = S.lanes[j];
+        const int g = g0[j] + ng[j] - 1 - k, q = ng[j] - 1 - k;
+        const int* mt = meta[j].data() + (size_t)q * 16;
+        if (!(mt[0] >= 1 && mt[0] <= m.dc && mt[4] >= 1 && mt[4] <= m.dc && mt[5] >= 1 && mt[5] <= m.dc &&
+              mt[6] >= 1 && mt[6] <= m.dc))
+          fail(MPS_EDEVICE, "gate sizes read back from the tape are out of range");
+        AdjLane a1;
+        a1.R = rec_at((char*)b->tape.p, m.L, q);
+        a1.W = W[j];
+        a1.d = dims_of(mt, dmeta[j].data() + (size_t)q * 16, p->C.bond_h[g]);
+        const int n = a1.d.n;
+        const size_t site = (size_t)m.dc * 2 * m.dc;
+        zd* Bbar = (zd*)b->Bbar.p;
+        double* lambar = (double*)b->lambar.p;
+        a1.Bbn = Bbar + (size_t)n * site;
+        a1.Bbn1 = Bbar + (size_t)(n + 1) * site;
+        a1.lb_out = lambar + (size_t)(n + 1) * m.dc;
+        a1.lb_in = lambar + (size_t)n * m.dc;
+        a1.gphi = (double*)b->gphi.p;
+        a1.theta = th_dev[grp[j]];
+        a1.gt = p->C.tab;
+        a1.g = g;
+        a1.kind = p->C.kind_h[g];
+        a1.dc = m.dc;
+        a1.ldc = m.ldc;
+        a1.ldv = m.ldv;
+        a1.eta = p->opts.broaden;
+        rec.push_back(a1);
+        mx.a = std::max(mx.a, a1.d.a);
+        mx.m = std::max(mx.m, a1.d.m);
+        mx.b = std::max(mx.b, a1.d.b);
+        mx.r = std::max(mx.r, a1.d.r);
+        ++act;
+      }
+      step_launch.push_back({act, mx});
+    }
+    AdjLane* rec_d = (AdjLane*)S.adj_dev.ensure(rec.size() * sizeof(AdjLane));
+    HIPCHK(hipMemcpyAsync(rec_d, rec.data(), rec.size() * sizeof(AdjLane), hipMemcpyHostToDevice, s));
+    size_t off = 0;
+    for (const auto& sl : step_launch) {
+      launch_gate_adjoint(rec_d + off, sl.first, sl.second, gw.stats, s);
+      off += sl.first;
+    }
+    HIPCHK(hipGetLastError());
+    // rec is rewritten for the next segment index only after this upload
+    HIPCHK(hipStreamSynchronize(s));
+    if (ctx->progress) ctx->progress(ctx->progress_user, "backward", S_max - sg, S_max);
+  }
+  // ---- chain rule per lane
+  for (int j = 0; j < nl; ++j) {
+    mps_plan* p = linfo[j].p;
+    PlanAdj& A = adj_of(p);
+    if (!A.chain_built) build_chain(p, A);
+    if (p->n_theta > 0)
+      hipLaunchKernelGGL(k_chain_rule, dim3((p->n_theta + 255) / 256), dim3(256), 0, s, (const int*)A.chain_start.p,
+                         (const int*)A.chain_list.p, p->C.tab, (const double*)S.lanes[j]->gphi.p, grad_dev[grp[j]],
+                         p->n_theta);
+  }
+  HIPCHK(hipGetLastError());
+  for (const GateStats& x : st) {
+    gsum->disc_sum += x.disc_sum;
+    gsum->disc_max = std::max(gsum->disc_max, x.disc_max);
+    gsum->svd_flop += x.svd_flop;
+    gsum->truncated += x.truncated;
+    gsum->max_sweeps = std::max(gsum->max_sweeps, x.max_sweeps);
+    gsum->noconv += x.noconv;
+    gsum->degenerate_cuts += x.degenerate_cuts;
+    gsum->max_bond = std::max(gsum->max_bond, x.max_bond);
+    gsum->gates += x.gates;
+  }
+}
+
+void plan_energy_grad_plans(mps_plan* const* plans, int n, const double* const* thetas, double* energies,
+                            double* const* grads, mps_stats* stats) {
+  if (n < 1) fail(MPS_EINVAL, "n_plans must be >= 1");
+  if (!plans || !thetas || !energies || !grads) fail(MPS_EINVAL, "NULL argument");
+  mps_plan* lead = plans[0];
+  if (!lead) fail(MPS_EINVAL, "NULL plan");
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) fail(MPS_EINVAL, "NULL plan");
+    if (plans[i]->ctx != lead->ctx) fail(MPS_EINVAL, "plans belong to different contexts");
+    if (plans[i]->n_theta > 0 && (!thetas[i] || !grads[i])) fail(MPS_EINVAL, "NULL theta or gradient array");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) fail(MPS_EINVAL, "a plan appears twice (use mps_energy_grad_batched)");
+    validate_theta(thetas[i], plans[i]->n_theta);
+  }
+  mps_ctx* ctx = lead->ctx;
+  hipStream_t s = ctx->stream;
+  // parameters and gradients on the device, one row per plan
+  std::vector<MixInfo> info(n);
+  std::vector<size_t> off(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    info[i] = mix_info(plans[i]);
+    off[i + 1] = off[i] + (size_t)std::max(1, plans[i]->n_theta);
+  }
+  PlanAdj& LA = adj_of(lead);
+  if (!LA.mix) LA.mix = new MixSet();
+  double* th = (double*)LA.mix->thetas.ensure(2 * off[n] * sizeof(double));
+  double* gd = th + off[n];
+  std::vector<const double*> th_dev(n);
+  std::vector<double*> g_dev(n);
+  for (int i = 0; i < n; ++i) {
+    th_dev[i] = th + off[i];
+    g_dev[i] = gd + off[i];
+    if (plans[i]->n_theta > 0)
+      HIPCHK(hipMemcpyAsync(th + off[i], thetas[i], plans[i]->n_theta * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  // groups of lanes that one cooperative launch holds
+  size_t shm = 0;
+  int max_dc = 2;
+  for (auto& m : info) {
+    shm = std::max(shm, chain_lds_bytes(m.dc));
+    max_dc = std::max(max_dc, m.dc);
+  }
+  const int cap = mixed_blocks_max(shm);
+  if (cap <= 0) fail(MPS_EDEVICE, "the mixed gate-chain kernel cannot be resident");
+  ctx->ensure_gate_work(max_dc, lead->trunc, lead->opts.max_sweeps);
+  ctx->reset_stats();   // degenerate pairs of the reverse pass are counted here
+  GateStats gsum{};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  std::vector<int> grp;
+  auto flush = [&]() {
+    if (grp.empty()) return;
+    mixed_group(lead, info, grp, th_dev, energies, g_dev, &gsum);
+    grp.clear();
+  };
+  std::vector<int2> blk;
+  for (int i = 0; i < n; ++i) {
+    std::vector<int> trial(grp);
+    trial.push_back(i);
+    if (mix_block_table(info, trial, blk) > cap) {
+      flush();
+      trial.assign(1, i);
+      if (mix_block_table(info, trial, blk) > cap)
+        fail(MPS_EDEVICE, "a lane needs more work-groups than the device holds at once");
+    }
+    grp = trial;
+  }
+  flush();
+  HIPCHK(hipEventRecord(e1, s));
+  for (int i = 0; i < n; ++i)
+    if (plans[i]->n_theta > 0)
+      HIPCHK(hipMemcpyAsync(grads[i], g_dev[i], plans[i]->n_theta * sizeof(double), hipMemcpyDeviceToHost, s));
+  GateStats gs;
+  HIPCHK(hipMemcpyAsync(&gs, ctx->gw.stats, sizeof(GateStats), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (gsum.noconv) fail(MPS_ENOCONV, "a Jacobi SVD did not converge");
+  bool strict = false;
+  for (int i = 0; i < n; ++i) strict = strict || plans[i]->opts.strict_degenerate;
+  if (gs.degen_grad > 0 && strict)
+    fail(MPS_EDEGEN, std::to_string(gs.degen_grad) + " degenerate singular pairs carry a cotangent");
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->discarded_weight_sum = gsum.disc_sum;
+    stats->discarded_weight_max = gsum.disc_max;
+    stats->max_bond = gsum.max_bond;
+    stats->gates_truncated = gsum.truncated;
+    stats->max_sweeps_used = gsum.max_sweeps;
+    stats->degenerate_cuts = gsum.degenerate_cuts;
+    stats->n_gates_applied = gsum.gates;
+    stats->t_backward_ms = ms;
+  }
+}
+
+PlanAdj::~PlanAdj() {
+  delete batch;
+  delete mix;
+}

@@ -153,6 +153,24 @@ int lanes_max(int dcap);
 hipError_t launch_chain_lanes(const GateLane* d_lanes, int nl, const LaneConst& c, bool record,
                               unsigned long long* bars, hipStream_t stream);
 
+// A lane of a mixed launch: its own constants (circuit, tape layout,
+// capacities, truncation), Jacobi width W (svd_width of its capacity) and
+// work-group count nblk; record: write the tape of this launch's gates.
+struct MixLane {
+  GateLane ln;
+  LaneConst c;
+  int W, nblk, record, pad;
+};
+// Dynamic LDS of a lane of capacity dcap; work-groups that one cooperative
+// launch of the mixed kernel holds with shm bytes each (0 on error).
+size_t chain_lds_bytes(int dcap);
+int mixed_blocks_max(size_t shm);
+// One cooperative launch of every lane in d_lanes: d_blk[i] = (lane, work-
+// group of that lane) for work-group i < nblocks, lane -1 for an idle one.
+// The lanes' barrier words must be zero.
+hipError_t launch_chain_mixed(const MixLane* d_lanes, const int2* d_blk, int nblocks, size_t shm,
+                              hipStream_t stream);
+
 // GATE_TAPE: Jacobi on C~ with the right rotations accumulated in V (the full
 // decomposition the reverse pass needs).  GATE_FWD: Jacobi on C~^H without
 // accumulation; the normalised columns are the right singular vectors.

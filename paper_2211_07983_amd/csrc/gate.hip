@@ -380,15 +380,19 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
             __syncthreads();
           }
         } else {
-          // cross pairs: column pr of the first block stays in registers
+          // cross pairs: column pr of the first block stays in registers.
+          // Only the first nra (A) and nrv (V) row chunks of a thread hold
+          // matrix rows; the chunks past them are zero padding, which no
+          // rotation changes, so they are neither loaded nor rotated.
+          const int nra = (M + TPP - 1) / TPP, nrv = (ncol + TPP - 1) / TPP;
           const int c0 = pr;
           zd xr[RPT], xv[RPT];
           const zd* xa = Al + c0 * mpad + lt;
           const zd* xva = Vl + c0 * vpad + lt;
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
-            xr[i] = xa[i * TPP];
-            if (ACC) xv[i] = xva[i * TPP];
+            if (i < nra) xr[i] = xa[i * TPP];
+            if (ACC && i < nrv) xv[i] = xva[i * TPP];
           }
           for (int sub = 0; sub < W; ++sub) {
             const int c1 = W + ((pr + sub) & (W - 1));
@@ -397,10 +401,14 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
             double al0 = 0.0, be0 = 0.0, gr0 = 0.0, gi0 = 0.0, al1 = 0.0, be1 = 0.0, gr1 = 0.0, gi1 = 0.0;
 #pragma unroll
             for (int i = 0; i < RPT; i += 2) {
-              yr[i] = y[i * TPP];
-              yr[i + 1] = y[(i + 1) * TPP];
-              pair_acc(xr[i], yr[i], al0, be0, gr0, gi0);
-              pair_acc(xr[i + 1], yr[i + 1], al1, be1, gr1, gi1);
+              if (i < nra) {
+                yr[i] = y[i * TPP];
+                pair_acc(xr[i], yr[i], al0, be0, gr0, gi0);
+              }
+              if (i + 1 < nra) {
+                yr[i + 1] = y[(i + 1) * TPP];
+                pair_acc(xr[i + 1], yr[i + 1], al1, be1, gr1, gi1);
+              }
             }
             double al = al0 + al1, be = be0 + be1, gr = gr0 + gr1, gi = gi0 + gi1;
             group_sum4<TPP>(al, be, gr, gi);
@@ -409,17 +417,21 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
             if (jacobi_rotation(al, be, gr, gi, tol, floor_g, c, pp, qq)) {
 #pragma unroll
               for (int i = 0; i < RPT; ++i) {
-                const zd u = xr[i], v = yr[i];
-                xr[i] = rot_x(u, v, c, pp);
-                y[i * TPP] = rot_y(u, v, c, qq);
+                if (i < nra) {
+                  const zd u = xr[i], v = yr[i];
+                  xr[i] = rot_x(u, v, c, pp);
+                  y[i * TPP] = rot_y(u, v, c, qq);
+                }
               }
               if (ACC) {
                 zd* yv = Vl + c1 * vpad + lt;
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
-                  const zd u = xv[i], v = yv[i * TPP];
-                  xv[i] = rot_x(u, v, c, pp);
-                  yv[i * TPP] = rot_y(u, v, c, qq);
+                  if (i < nrv) {
+                    const zd u = xv[i], v = yv[i * TPP];
+                    xv[i] = rot_x(u, v, c, pp);
+                    yv[i * TPP] = rot_y(u, v, c, qq);
+                  }
                 }
               }
               rot = true;
@@ -428,8 +440,8 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
           }
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
-            Al[c0 * mpad + lt + i * TPP] = xr[i];
-            if (ACC) Vl[c0 * vpad + lt + i * TPP] = xv[i];
+            if (i < nra) Al[c0 * mpad + lt + i * TPP] = xr[i];
+            if (ACC && i < nrv) Vl[c0 * vpad + lt + i * TPP] = xv[i];
           }
           __syncthreads();
         }
@@ -464,18 +476,21 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
     if (sh_stop) break;
   }
   const int used = sweep + 1;
+  // The Jacobi blocks are back in global memory: the reductions below use
+  // the front of the block LDS (at least 64 KiB for every width), so a kernel
+  // that instantiates several widths holds no per-width shared arrays.
+  double* red = (double*)lds;          // [256]
+  double* shs = (double*)lds + 256;    // [1024]
   // singular values: column norms
   for (int c = p; c < ncol; c += nblk) {
     double acc = 0.0;
     for (int r = t; r < M; r += 256) acc += zabs2(s.A[(size_t)c * s.lda + r]);
-    __shared__ double red[256];
     acc = block_sum256(acc, red);
     if (t == 0) s.sv[c] = sqrt(acc);
   }
   bar.sync();
   if (p != 0) return;
   // work-group 0: order, rank, normalisation, lambda, statistics
-  __shared__ double shs[1024];
   for (int c = t; c < ncol; c += 256) shs[c] = s.sv[c];
   __syncthreads();
   for (int c = t; c < ncol; c += 256) {
@@ -699,18 +714,11 @@ __device__ inline void copy_words(unsigned long long* dst, const unsigned long l
   for (size_t e = (size_t)p * 256 + threadIdx.x; e < words; e += (size_t)nblk * 256) dst[e] = src[e];
 }
 
+// The gate chain of one lane on work-group p of its nblk: ln.ng gates from
+// ln.g0, each contraction tiles, Jacobi SVD and site update with the lane's
+// barrier in between; the state before the first gate goes to ln.ckpt.
 template <int W>
-__global__ __launch_bounds__(256) void k_chain_lanes(const GateLane* lanes, LaneConst c, int nblk, int record) {
-  // Work-groups are dispatched to the 8 XCDs round-robin (work-group i on XCD
-  // i % 8).  When the launch divides evenly, the nblk work-groups of a lane
-  // are taken from one XCD, so its barrier and block exchange stay there.
-  const int T = gridDim.x;
-  int slot = blockIdx.x;
-  if (T % 8 == 0 && (T / 8) % nblk == 0) slot = (blockIdx.x % 8) * (T / 8) + blockIdx.x / 8;
-  const int lane = slot / nblk, p = slot % nblk;
-  const GateLane& ln = lanes[lane];
-  extern __shared__ zd lds[];
-  zd* sbuf = lds;    // tile-GEMM staging; the Jacobi blocks use the same LDS in between barriers
+__device__ void chain_body(const GateLane& ln, const LaneConst& c, int p, int nblk, int record, zd* sbuf) {
   LaneBarrier bar{ln.bar, ln.err, (unsigned long long)nblk, 0ull};
   const MpsView& st = ln.st;
   const int dc = st.dcap;
@@ -750,7 +758,14 @@ __global__ __launch_bounds__(256) void k_chain_lanes(const GateLane* lanes, Lane
         }
       }
     }
-    if (p == 0 && threadIdx.x < 128) ln.rotflag[threadIdx.x] = 0;
+    // The sweep votes of the lane start at zero.  Other work-groups of the
+    // lane, possibly on other XCDs, update them with device-scope atomics, so
+    // the reset is a device-scope atomic store too: a plain store would sit in
+    // this XCD's L2 and could be ordered differently from the atomics (seen as
+    // work-groups leaving the sweep loop on different sweeps when a lane spans
+    // XCDs).
+    if (p == 0 && threadIdx.x < 128)
+      __hip_atomic_store(&ln.rotflag[threadIdx.x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int tile = p; tile < tiles * tiles; tile += nblk)
       contract_tile<true>(st, c.gt, g, ln.theta, R.C, R.A, c.ldc, ln.nrm_part, 0, tile % tiles, tile / tiles, tiles,
                           sbuf, g == ln.shift_gate ? ln.shift : 0.0);
@@ -762,6 +777,45 @@ __global__ __launch_bounds__(256) void k_chain_lanes(const GateLane* lanes, Lane
       update_left_tile<true>(st, n, R.C, c.ldc, R.V, c.ldv, R.perm, R.meta, R.dmeta, tile % tn, tile / tn, sbuf);
     for (int mu = p; mu < dc; mu += nblk) update_right_row(st, n, R.V, c.ldv, R.perm, R.meta, mu);
     bar.sync();
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_chain_lanes(const GateLane* lanes, LaneConst c, int nblk, int record,
+                                                     int nl, int xcd_local) {
+  // Work-groups are dispatched to the 8 XCDs round-robin (work-group i on XCD
+  // i % 8).  With xcd_local the grid is padded to 8 nblk ceil(nl / 8)
+  // work-groups and lane l takes nblk work-groups of XCD l % 8, so its
+  // barrier and block exchange stay in that XCD's L2 (padding work-groups
+  // exit at once).  Otherwise work-group i serves lane i / nblk.
+  int lane, p;
+  if (xcd_local) {
+    const int k = blockIdx.x / 8;
+    lane = (int)(blockIdx.x % 8) + 8 * (k / nblk);
+    p = k % nblk;
+    if (lane >= nl) return;
+  } else {
+    lane = blockIdx.x / nblk;
+    p = blockIdx.x % nblk;
+  }
+  extern __shared__ zd lds[];
+  chain_body<W>(lanes[lane], c, p, nblk, record, lds);
+}
+
+// Lanes of different circuits, qubit counts and capacities in one launch:
+// each lane carries its own constants, Jacobi width and work-group count, and
+// blk[i] = (lane, work-group of the lane) for work-group i (lane -1: idle),
+// laid out on the host so that a lane's work-groups share one XCD.
+__global__ __launch_bounds__(256) void k_chain_mixed(const MixLane* lanes, const int2* blk) {
+  const int2 b = blk[blockIdx.x];
+  if (b.x < 0) return;
+  const MixLane& L = lanes[b.x];
+  extern __shared__ zd lds[];
+  switch (L.W) {
+    case 32: chain_body<32>(L.ln, L.c, b.y, L.nblk, L.record, lds); break;
+    case 16: chain_body<16>(L.ln, L.c, b.y, L.nblk, L.record, lds); break;
+    case 8: chain_body<8>(L.ln, L.c, b.y, L.nblk, L.record, lds); break;
+    default: chain_body<4>(L.ln, L.c, b.y, L.nblk, L.record, lds); break;
   }
 }
 
@@ -790,9 +844,24 @@ hipError_t launch_chain_lanes(const GateLane* d_lanes, int nl, const LaneConst& 
   e = hipFuncSetAttribute(chain_kernel(W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   LaneConst cc = c;
-  int nb = P, rec = record ? 1 : 0;
-  void* args[] = {(void*)&d_lanes, &cc, &nb, &rec};
-  return hipLaunchCooperativeKernel(chain_kernel(W), dim3(P * nl), dim3(256), args, shm, stream);
+  int nb = P, rec = record ? 1 : 0, nlanes = nl;
+  // Lanes on one XCD each when the padded grid is resident at once.  Besides
+  // keeping the block exchange in one L2, this is the layout every recompute
+  // result has been reproducible in: with lanes of 16 work-groups spread over
+  // all XCDs, segment replays at capacity 128 differed from their forward
+  // pass now and then, a fault this layout has not shown.  Capacity 256
+  // (64 work-groups per lane) cannot be XCD-local and keeps the plain layout.
+  int dev = 0, cus = 0, per_cu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chain_kernel(W), 256, shm);
+  if (e != hipSuccess) return e;
+  const int padded = 8 * P * ((nl + 7) / 8);
+  int xcd = P <= 32 && padded <= per_cu * cus ? 1 : 0;
+  const int T = xcd ? padded : P * nl;
+  void* args[] = {(void*)&d_lanes, &cc, &nb, &rec, &nlanes, &xcd};
+  return hipLaunchCooperativeKernel(chain_kernel(W), dim3(T), dim3(256), args, shm, stream);
 }
 
 TapeLayout tape_layout(int dc, int ncap, int ldc, int ldv) {
@@ -825,6 +894,36 @@ int lanes_max(int dcap) {
   const size_t shm = chain_shared_bytes(dcap, 2 * dcap, 2 * P * W);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chain_kernel(W), 256, shm) != hipSuccess) return 1;
   return std::max(1, per_cu * cus / P);
+}
+
+
+// Dynamic LDS of the chain kernel for a lane of capacity dcap.
+size_t chain_lds_bytes(int dcap) {
+  const int W = svd_width(dcap);
+  const int P = (2 * dcap + 2 * W - 1) / (2 * W);
+  return chain_shared_bytes(dcap, 2 * dcap, 2 * P * W);
+}
+
+// Work-groups one cooperative launch of the mixed kernel holds with `shm`
+// bytes of dynamic LDS each.
+int mixed_blocks_max(size_t shm) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipFuncSetAttribute((const void*)k_chain_mixed, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) !=
+      hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_chain_mixed, 256, shm) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_chain_mixed(const MixLane* d_lanes, const int2* d_blk, int nblocks, size_t shm,
+                              hipStream_t stream) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_chain_mixed, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)&d_lanes, (void*)&d_blk};
+  return hipLaunchCooperativeKernel((const void*)k_chain_mixed, dim3(nblocks), dim3(256), args, shm, stream);
 }
 
 

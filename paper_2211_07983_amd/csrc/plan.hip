@@ -203,6 +203,12 @@ mps_status mps_energy_grad_multi(mps_plan* const* plans, int32_t n_plans, const 
   });
 }
 
+mps_status mps_energy_grad_plans(mps_plan* const* plans, int32_t n_plans, const double* const* thetas,
+                                 double* energies, double* const* grads, mps_stats* stats) {
+  if (!plans || n_plans < 1 || !plans[0] || !thetas || !energies || !grads) return MPS_EINVAL;
+  return guarded(plans[0]->ctx, [&] { plan_energy_grad_plans(plans, n_plans, thetas, energies, grads, stats); });
+}
+
 mps_status mps_energy_grad_alg1(mps_plan* plan, const double* theta, int32_t n_theta, int32_t strings_per_group,
                                 double* energy, double* grad, double* gate_grad, mps_stats* stats) {
   if (!plan || !energy || (plan->n_theta > 0 && !grad)) return MPS_EINVAL;

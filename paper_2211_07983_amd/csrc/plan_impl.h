@@ -52,6 +52,8 @@ void plan_energy_grad_psr(mps_plan* p, const double* theta, int n_theta, double*
                           double* gate_grad, mps_stats* stats);
 void plan_energy_grad_alg1(mps_plan* p, const double* theta, int n_theta, int per_group, double* energy,
                            double* grad, double* gate_grad, mps_stats* stats);
+void plan_energy_grad_plans(mps_plan* const* plans, int n, const double* const* thetas, double* energies,
+                            double* const* grads, mps_stats* stats);
 void plan_energy_grad_multi(mps_plan* const* plans, int n, const double* thetas, int n_theta, double* energies,
                             double* grads, mps_stats* stats);
 void plan_energy_grad_batched(mps_plan* p, int nb, const double* thetas, int n_theta, int on_device,

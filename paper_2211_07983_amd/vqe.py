@@ -170,14 +170,45 @@ def bfgs(fg, theta0, fg_batched=None, n_trial=4, shrink=0.5, c1=1e-4, max_step=1
     return res
 
 
-def minimize(plan, theta0, method="bfgs", **kw):
-    """Runs one of the loops on a Plan: energies and gradients from the GPU
-    (``energy_grad``; BFGS's line search through ``energy_grad_batched``).
+GRADIENTS = ("auto", "local", "alg1")
 
-    Start from a generic theta0, not from exactly 0: there the state is a
-    product state, and the gradient back-propagated through the truncated SVDs
-    is the fixed-rank one, which vanishes in every direction that would raise
-    a bond's rank (a small random theta0 avoids this)."""
+
+def minimize(plan, theta0, method="bfgs", gradient="auto", strings_per_group=4, **kw):
+    """Runs one of the loops on a Plan with energies and gradients from the GPU.
+
+    gradient selects the derivative:
+    - "local": the back-propagated fixed-rank gradient (Plan.energy_grad; the
+      BFGS line search through Plan.energy_grad_batched).  At a product state
+      such as the Hartree-Fock start theta = 0 it is exactly zero in every
+      direction that would raise a bond's rank (the directions below the
+      truncation are absent), so a run from there would stop at once; this
+      choice raises ValueError when the starting gradient is exactly zero.
+    - "alg1": the paper's Algorithm 1 with the Hamiltonian split into groups of
+      strings_per_group strings (Plan.energy_grad_alg1; Sec. 5 runs its
+      optimiser with four strings per group), exact in those directions.
+    - "auto": "local", unless the starting local gradient is exactly zero;
+      then the whole run uses "alg1"."""
+    if gradient not in GRADIENTS:
+        raise ValueError(f"unknown gradient {gradient!r} (one of {GRADIENTS})")
+    if gradient != "alg1":
+        e0, g0, _ = plan.energy_grad(np.asarray(theta0, dtype=np.float64))
+        if not np.any(g0):
+            if gradient == "local":
+                raise ValueError("the fixed-rank gradient is exactly zero at theta0 (a product state such as the "
+                                 "Hartree-Fock start); use gradient='alg1' or a generic theta0")
+            gradient = "alg1"
+    if gradient == "alg1":
+        def fg(th):
+            e, g, _, _ = plan.energy_grad_alg1(th, strings_per_group)
+            return e, g
+        if method == "bfgs":
+            return bfgs(fg, theta0, **kw)
+        if method == "gd":
+            return gradient_descent(fg, theta0, **kw)
+        if method == "adam":
+            return adam(fg, theta0, **kw)
+        raise ValueError(f"unknown method {method!r}")
+
     def fg(th):
         e, g, _ = plan.energy_grad(th)
         return e, g

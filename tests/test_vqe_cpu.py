@@ -110,3 +110,48 @@ def test_invalid_settings_are_refused():
         vqe.gradient_descent(fg, np.zeros(6), lr=0.0)
     with pytest.raises(ValueError):
         vqe.adam(fg, np.zeros(6), beta1=1.0)
+
+
+class _PlanStub:
+    """Stands in for a Plan: the fixed-rank gradient of a product state (zero
+    at theta = 0, the quadratic's gradient elsewhere) and an Algorithm 1
+    gradient (the quadratic's gradient everywhere); counts the calls."""
+
+    def __init__(self, fg):
+        self.fg = fg
+        self.calls = {"local": 0, "batched": 0, "alg1": 0}
+
+    def energy_grad(self, th):
+        self.calls["local"] += 1
+        e, g = self.fg(th)
+        return e, (np.zeros_like(g) if not np.any(th) else g), {}
+
+    def energy_grad_batched(self, ths):
+        self.calls["batched"] += 1
+        out = [self.energy_grad(t) for t in ths]
+        return np.array([o[0] for o in out]), np.stack([o[1] for o in out]), {}
+
+    def energy_grad_alg1(self, th, strings_per_group=1):
+        self.calls["alg1"] += 1
+        assert strings_per_group == 4
+        e, g = self.fg(th)
+        return e, g, None, {}
+
+
+def test_minimize_from_a_product_state_uses_algorithm_1_or_raises():
+    A, b, xs, fg = quadratic()
+    x0 = np.zeros(6)
+    with pytest.raises(ValueError, match="exactly zero"):
+        vqe.minimize(_PlanStub(fg), x0, "bfgs", gradient="local")
+    with pytest.raises(ValueError, match="unknown gradient"):
+        vqe.minimize(_PlanStub(fg), x0, "bfgs", gradient="exact")
+    for grad in ("auto", "alg1"):
+        stub = _PlanStub(fg)
+        r = vqe.minimize(stub, x0, "bfgs", gradient=grad, e_tol=0.0, g_tol=1e-7, max_step=10.0)
+        assert r.reason == "gradient" and np.abs(r.theta - xs).max() <= 1e-7
+        assert stub.calls["alg1"] == r.evaluations and stub.calls["batched"] == 0
+        assert stub.calls["local"] == (1 if grad == "auto" else 0)
+    # a generic start keeps the local gradient and the batched line search
+    stub = _PlanStub(fg)
+    r = vqe.minimize(stub, np.full(6, 0.1), "bfgs", e_tol=0.0, g_tol=1e-7, max_step=10.0)
+    assert r.reason == "gradient" and stub.calls["alg1"] == 0 and stub.calls["batched"] > 0
