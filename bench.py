@@ -117,13 +117,6 @@ def nproc_threads():
     return max(1, n)
 
 
-def one_thread():
-    """BLAS limited to one thread: the oracle's small matrices run slower with
-    more (oversubscription), and one core is a defined setting to report."""
-    from threadpoolctl import threadpool_limits
-    return threadpool_limits(1)
-
-
 def cpu_baseline_full(prob, gates, eps):
     """The FP64 oracle (T3) on the whole workload: one energy + gradient."""
     from oracle import mps as T3
@@ -136,28 +129,54 @@ def cpu_baseline_full(prob, gates, eps):
             "seconds_per_eval": dt}
 
 
-def cpu_baseline_settings(prob, gates, eps, full):
+def cpu_baseline_settings(workload, eps, timeout_s=150.0):
     """The oracle in the two settings of the timing protocol: BLAS on one thread
-    and on nproc threads.  `value`/`cores` are the faster setting's; both are
-    listed under `settings` with the host's core count and CPU model."""
-    from threadpoolctl import threadpool_limits
+    and on nproc threads, each in a child process whose thread count is fixed
+    by the environment before NumPy loads (changing a loaded BLAS's pool in
+    flight has crashed long oracle runs).  `value`/`cores` are the faster
+    setting's; both are listed under `settings` with the host's core count and
+    CPU model.  A setting that fails is listed with its error."""
+    import subprocess
     runs = []
     for n in (1, nproc_threads()):
         if runs and n == runs[0]["requested_threads"]:
             break
-        with threadpool_limits(limits=n):
-            r = cpu_baseline_full(prob, gates, eps) if full else cpu_baseline_sample(prob, gates, eps)
-            r["thread_pools"] = host_info()["thread_pools"]
+        env = dict(os.environ, OPENBLAS_NUM_THREADS=str(n), OMP_NUM_THREADS=str(n), MKL_NUM_THREADS=str(n))
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--workload", workload, "--eps", repr(eps)]
+        try:
+            p = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                               timeout=timeout_s)
+            if p.returncode != 0:
+                raise RuntimeError(f"exit {p.returncode}: {p.stderr.strip()[-300:]}")
+            r = json.loads(p.stdout.strip().splitlines()[-1])
+        except Exception as exc:   # a failed setting is reported, not fatal to the line
+            log(f"cpu baseline with {n} thread(s) failed: {exc}")
+            runs.append({"requested_threads": n, "error": str(exc)[:300]})
+            continue
         r["requested_threads"] = n
         log(f"cpu baseline, {n} requested / {r['cores']} reported BLAS thread(s): {r['value']:.3e} evals/s "
             f"({r['seconds_per_eval']:.1f} s/eval); pools {r['thread_pools']}")
         runs.append(r)
-    best = max(runs, key=lambda r: r["value"])
-    out = dict(best)
-    out["settings"] = [{"cores": r["cores"], "requested_threads": r["requested_threads"], "value": r["value"],
-                        "seconds_per_eval": r["seconds_per_eval"], "thread_pools": r["thread_pools"]} for r in runs]
+    ok = [r for r in runs if "value" in r]
+    if not ok:
+        return None
+    out = dict(max(ok, key=lambda r: r["value"]))
+    out["settings"] = [{k: r[k] for k in ("cores", "requested_threads", "value", "seconds_per_eval", "thread_pools",
+                                          "error") if k in r} for r in runs]
     out["host"] = host_info()
     return out
+
+
+def cpu_child(args):
+    """--cpu-child: one CPU-baseline setting of the workload (the whole
+    evaluation for c1/c2, a bounded sample otherwise); prints one JSON line.
+    Touches no GPU."""
+    from vqe_inputs import configs
+    prob, gates = configs.load(args.workload, eps=args.eps)
+    full = args.workload in ("c1", "c2")
+    r = cpu_baseline_full(prob, gates, prob.eps) if full else cpu_baseline_sample(prob, gates, prob.eps)
+    r["thread_pools"] = host_info()["thread_pools"]
+    print(json.dumps(r), flush=True)
 
 
 def cpu_baseline_sample(prob, gates, eps, budget_s=25.0):
@@ -465,6 +484,65 @@ def instances_phase(args):
     print(json.dumps(line), flush=True)
 
 
+def mixed_phase(args):
+    """The batched-instance set across size classes: every instance with at
+    most args.max_qubits qubits (its own circuit, D and Hamiltonian) in one
+    mps_energy_grad_plans call, whose lanes share the gate-chain launches.
+    The sequential reference evaluates one instance per (qubits, D) class on
+    its own and weights it by the class's count (a sample, stated in the
+    line); the full sequential run is the sum of those per-class times."""
+    import numpy as np
+    from vqe_inputs import configs
+    from vqe_inputs.compile import compile_problem
+    from vqe_inputs.problem import make_problem
+    from paper_2211_07983_amd import Context, Plan, energy_grad_plans
+    members = [i for i, (n, ne, D, s1, s2) in enumerate(configs.batched_instances()) if n <= args.max_qubits]
+    ctx = Context(0)
+    probs, plans, circuits = [], [], {}
+    for i in members:
+        n, ne, D, s1, s2 = configs.batched_instances()[i]
+        p = make_problem(f"c4_{i}", n, ne, D, args.eps, s1, s2, 0.05)
+        g = circuits.get((n, ne)) or compile_problem(p)
+        circuits[(n, ne)] = g
+        probs.append(p)
+        plans.append(Plan(ctx, p.occ, g, p.n_qubits, p.ham_x, p.ham_z, p.ham_c, p.c0, p.bond_dim, p.eps,
+                          ckpt_gates=args.ckpt_gates))
+    classes = {}
+    for k, p in enumerate(probs):
+        classes.setdefault((p.n_qubits, p.bond_dim), []).append(k)
+    log(f"{len(plans)} instances up to {args.max_qubits} q: classes "
+        + ", ".join(f"{q}q D{d} x{len(v)}" for (q, d), v in sorted(classes.items())))
+    t0 = time.perf_counter()
+    e_m, g_m, st = energy_grad_plans(plans, [p.theta for p in probs])
+    t_mixed = time.perf_counter() - t0
+    log(f"one call: {len(plans)} instances in {t_mixed:.2f}s, max bond {st['max_bond']}")
+    seq_est, worst, per_class = 0.0, 0.0, {}
+    for (q, d), ks in sorted(classes.items()):
+        k = ks[0]
+        t0 = time.perf_counter()
+        e1, g1, _ = plans[k].energy_grad(probs[k].theta)
+        dt = time.perf_counter() - t0
+        worst = max(worst, abs(e1 - e_m[k]) / abs(e1), float(np.abs(g1 - g_m[k]).max() / np.abs(g1).max()))
+        per_class[f"{q}q_D{d}"] = {"count": len(ks), "instance": members[k], "single_s": dt}
+        seq_est += dt * len(ks)
+        log(f"  {q} q, D={d}: instance {members[k]} alone {dt:.2f}s (x{len(ks)})")
+    line = {
+        "metric": "instance energy+grad evals/s, batched-instance set across size classes in shared launches",
+        "value": len(plans) / t_mixed, "unit": "instance-evals/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * t_mixed, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded per-instance integrals and theta)",
+        "config": {"workload": f"batched-instance set, the {len(plans)} instances with at most {args.max_qubits} "
+                               f"qubits ({len(classes)} (qubits, D) classes), eps={args.eps:g}",
+                   "instances": members, "classes": per_class,
+                   "sequential_estimate_s": seq_est,
+                   "sequential_note": "one instance per class timed alone, times the class count",
+                   "speedup_vs_sequential_estimate": seq_est / t_mixed,
+                   "max_rel_diff_vs_single": worst, "max_bond": st["max_bond"]},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def alg1_phase(args):
     """Algorithm 1 (one Pauli string per group, 2 N_h reverse walks) against
     back-propagation on the same plan: 6 qubits (3 orbitals, 2 electrons),
@@ -521,7 +599,9 @@ def main():
                          "not started; the line reports the steps that ran)")
     ap.add_argument("--cpu-reserve-s", type=float, default=90.0,
                     help="share of --budget-s held back for the CPU baseline")
-    ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr", "vqe", "instances", "alg1"], default="evalgrad")
+    ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr", "vqe", "instances", "mixed", "alg1"],
+                    default="evalgrad")
+    ap.add_argument("--max-qubits", type=int, default=16, help="--phase mixed: largest instance size taken")
     ap.add_argument("--class-qubits", type=int, default=12, help="--phase instances: qubit count of the class")
     ap.add_argument("--class-d", type=int, default=64, help="--phase instances: bond dimension of the class")
     ap.add_argument("--vqe-iters", type=int, default=100, help="--phase vqe: iteration limit")
@@ -529,10 +609,14 @@ def main():
                     help="evalgrad phase: 0 plain FP64, 1 Pauli sweeps and sweep adjoint on FP32 matrix cores")
     ap.add_argument("--prefix-gates", type=int, default=3000,
                     help="--phase sweep: gates applied before the sweeps are timed")
+    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for hardware byte counters)")
     args = ap.parse_args()
+    if args.cpu_child:
+        cpu_child(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the hot path runs on a single GPU in this build "
               "(the multi-GPU split is a design note, not built); use --gpus 1", file=sys.stderr)
@@ -551,6 +635,9 @@ def main():
         return
     if args.phase == "instances":
         instances_phase(args)
+        return
+    if args.phase == "mixed":
+        mixed_phase(args)
         return
     if args.phase == "alg1":
         alg1_phase(args)
@@ -651,7 +738,7 @@ def main():
     ctx.close()
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_settings(prob, gates, prob.eps, full=args.workload in ("c1", "c2"))
+        cpu = cpu_baseline_settings(args.workload, prob.eps)
     line = {
         "metric": METRIC,
         "value": value,

@@ -40,6 +40,11 @@ import math
 import numpy as np
 import scipy.linalg as sla
 
+# LAPACK driver of the full SVD.  gesvd is the reference.  gesdd, another
+# backward-stable SVD, serves only to measure how far the choice of a correct
+# SVD moves a result where truncation makes it ill-conditioned.
+SVD_DRIVER = "gesvd"
+
 ZZ = np.diag([1.0, -1.0, -1.0, 1.0]).astype(np.complex128)
 
 
@@ -92,7 +97,7 @@ class MPS:
         Cm = C.reshape(2 * a, 2 * b)
         lam_in = self.lam[n]
         M = (lam_in[:, None, None, None] * C).reshape(2 * a, 2 * b)
-        U, s, Wh = sla.svd(M, full_matrices=True, lapack_driver="gesvd")
+        U, s, Wh = sla.svd(M, full_matrices=True, lapack_driver=SVD_DRIVER)
         r = max(1, min(D, int(np.count_nonzero(s > eps)))) if rank is None else int(rank)
         self.ranks.append(r)
         nu = float(np.sqrt(np.sum(s[:r] ** 2)))

@@ -100,20 +100,26 @@ def batched_instance(i):
 C4_PARITY = (3, 5, 8, 14, 17)
 
 
-def batched_instance_paper(i, broaden=0.0):
+def batched_instance_paper(i, broaden=0.0, driver="gesvd"):
     """Instance i of the batched set at eps = 1e-6: energy, gradient (with the
     SVD adjoint's Lorentzian broadening eta = broaden, 0 = none), bonds,
-    discarded weight and the degenerate-cut count of the forward pass."""
+    discarded weight and the degenerate-cut count of the forward pass, with
+    the oracle's SVDs taken by the LAPACK driver `driver`."""
     from vqe_inputs.compile import compile_problem
     from vqe_inputs.problem import make_problem
     n, ne, D, s1, s2 = configs.batched_instances()[i]
     p = make_problem(f"c4_{i}", n, ne, D, configs.PAPER_EPS, s1, s2, 0.05)
     g = compile_problem(p)
-    E, grad, info = mps.energy_grad(p, g, p.theta, broaden=broaden)
-    _, finfo = mps.energy(p, g, p.theta)
-    return dict(n_qubits=n, D=D, eps=p.eps, broaden=broaden, E=E, grad=grad.tolist(), bonds=finfo["bonds"],
-                discarded_sum=float(sum(finfo["discarded"])), degenerate_cuts=int(finfo["degenerate_cuts"]),
-                n_gates=int(g.n_gates))
+    saved = mps.SVD_DRIVER
+    mps.SVD_DRIVER = driver
+    try:
+        E, grad, info = mps.energy_grad(p, g, p.theta, broaden=broaden)
+        _, finfo = mps.energy(p, g, p.theta)
+    finally:
+        mps.SVD_DRIVER = saved
+    return dict(n_qubits=n, D=D, eps=p.eps, broaden=broaden, driver=driver, E=E, grad=grad.tolist(),
+                bonds=finfo["bonds"], discarded_sum=float(sum(finfo["discarded"])),
+                degenerate_cuts=int(finfo["degenerate_cuts"]), n_gates=int(g.n_gates))
 
 
 C5_GRAD_PREFIX = 2000
@@ -177,6 +183,29 @@ ENTRIES.update({f"c4p_{i}": (lambda i=i: batched_instance_paper(i)) for i in C4_
 ENTRIES.update({f"c4p_{i}_b": (lambda i=i: batched_instance_paper(i, C2_BROADEN)) for i in (3, 8)})
 
 
+def rounding_variants(i, broaden):
+    """Instance i recomputed with rounding-level changes only: the SVDs by
+    gesvd and by gesdd, each with one BLAS thread and with eight (each run in a
+    child process whose BLAS pool the environment fixes).  Where truncation at
+    D makes E_D and g_D ill-conditioned (instance 3 cuts as close as 1.5e-7 s_1
+    on 2249 gates), these runs spread as far as any correct implementation
+    may land."""
+    import subprocess
+    out = []
+    for driver in ("gesvd", "gesdd"):
+        for threads in (1, 8):
+            env = dict(os.environ, OPENBLAS_NUM_THREADS=str(threads), OMP_NUM_THREADS=str(threads),
+                       MKL_NUM_THREADS=str(threads))
+            p = subprocess.run([sys.executable, os.path.abspath(__file__), "--variant", str(i), repr(broaden), driver],
+                               env=env, stdout=subprocess.PIPE, text=True, check=True)
+            r = json.loads(p.stdout.strip().splitlines()[-1])
+            out.append(dict(driver=driver, threads=threads, E=r["E"], grad=r["grad"]))
+    return dict(broaden=broaden, variants=out)
+
+
+ENTRIES["c4p_3_b_variants"] = lambda: rounding_variants(3, C2_BROADEN)
+
+
 def main(names):
     res = {}
     if os.path.exists(OUT):
@@ -192,4 +221,8 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:])
+    if sys.argv[1:2] == ["--variant"]:
+        r = batched_instance_paper(int(sys.argv[2]), float(sys.argv[3]), sys.argv[4])
+        print(json.dumps(dict(E=r["E"], grad=r["grad"])), flush=True)
+    else:
+        main(sys.argv[1:])

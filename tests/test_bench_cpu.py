@@ -17,7 +17,7 @@ def test_every_phase_is_offered():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0
-    for phase in ("evalgrad", "sweep", "psr", "vqe", "instances", "alg1"):
+    for phase in ("evalgrad", "sweep", "psr", "vqe", "instances", "mixed", "alg1"):
         assert phase in r.stdout
 
 
@@ -40,14 +40,14 @@ def test_instance_classes_share_their_circuit():
 
 def test_cpu_baseline_reports_both_thread_settings_and_the_host():
     """The CPU baseline times the oracle with BLAS on one thread and on the
-    nproc setting, and records the host's core counts and CPU model."""
+    nproc setting, each in a child process whose BLAS pool the environment
+    fixes, and records the host's core counts and CPU model."""
     sys.path.insert(0, ROOT)
     import bench
-    from vqe_inputs import configs
-    p, g = configs.load("c1")
-    r = bench.cpu_baseline_settings(p, g, p.eps, full=True)
+    r = bench.cpu_baseline_settings("c1", 1e-12)
     assert r["kind"] == "oracle" and r["unit"] == "evals/s" and r["value"] > 0
-    assert r["settings"][0]["cores"] == 1
+    assert all("error" not in s for s in r["settings"])
+    assert r["settings"][0]["requested_threads"] == 1 and r["settings"][0]["cores"] == 1
     assert r["cores"] in [s["cores"] for s in r["settings"]]
     assert r["value"] == max(s["value"] for s in r["settings"])
     host = r["host"]

@@ -65,11 +65,15 @@ def test_40_qubit_prefix_energy_matches_oracle(ctx):
 #     its plain g_D holds nearly degenerate kept pairs that carry cotangents
 #     (the oracle's own g_D moves by 3e-6 when eta = 1e-12), so the gradient is
 #     compared broadened (eta = 1e-8 on both sides).
-#  3: 12 q, D = 32, eps = 1e-6: truncates at D with cuts as close as 1.5e-7
-#     s_1; E_D itself moves by 1.5e-8 Ha between two LAPACK drivers (gesvd and
-#     gesdd) in the oracle, so E is held to 1e-6 Ha and the broadened gradient
-#     to 1e-5, the tolerances of the reduced-precision path.
-C4_CASES = [(4, False, 1e-10, 1e-8), (5, False, 1e-10, 1e-8), (8, True, 1e-10, 1e-8), (3, True, None, 1e-5)]
+#  3: 12 q, D = 32, eps = 1e-6: truncates at D on 2249 gates (discarded
+#     weight 3.3e-3) with cuts as close as 1.5e-7 s_1.  There E_D and g_D are
+#     fixed only up to rounding: the oracle itself, rerun with another LAPACK
+#     driver or BLAS thread count, moves E by up to ~2e-7 Ha and the broadened
+#     gradient by ~1e-3 of its largest entry.  The GPU's Jacobi SVD is one
+#     more such rounding, so it is held to twice the diameter of the oracle's
+#     own rounding variants (None).
+C4_CASES = [(4, False, 1e-10, 1e-8), (5, False, 1e-10, 1e-8), (8, True, 1e-10, 1e-8), (3, True, None, None)]
+SPREAD_FACTOR = 2.0
 
 
 @pytest.mark.parametrize("case", C4_CASES, ids=[f"instance{c[0]}" for c in C4_CASES])
@@ -110,10 +114,17 @@ def test_batched_set_instance_matches_oracle(ctx, case):
     # cancellation per gate on either side
     assert abs(disc - gold["discarded_sum"]) <= 1e-8 * gold["discarded_sum"] + 1e-15 * len(g.bond)
     if e_tol is None:
-        assert abs(e - gold["E"]) <= 1e-6
+        # conditioning-limited: the diameter of the oracle's rounding variants
+        runs = [gref] + golden()[f"c4p_{i}_b_variants"]["variants"]
+        gscale = max(1.0, np.abs(ref).max())
+        e_spread = max(abs(a["E"] - b["E"]) for a in runs for b in runs)
+        g_spread = max(np.abs(np.array(a["grad"]) - np.array(b["grad"])).max() for a in runs for b in runs) / gscale
+        print(f"  oracle rounding variants: E spread {e_spread:.2e}, grad spread {g_spread:.2e}")
+        assert abs(e - gref["E"]) <= SPREAD_FACTOR * e_spread
+        assert gerr <= SPREAD_FACTOR * g_spread
     else:
         assert rel(e, gold["E"]) <= e_tol
-    assert gerr <= g_tol
+        assert gerr <= g_tol
     if i == 4:
         eb, gb, _ = plan.energy_grad_batched(np.stack([p.theta, p.theta]))
         assert abs(eb[1] - e) <= 1e-13 * abs(e)
