@@ -236,7 +236,10 @@ __device__ inline void store_blocks(zd* dst, int ldd, const zd* src, int lsrc, i
 // barrier; barrier k completes when it reaches (k + 1) nblk.  The launches
 // are cooperative, so every work-group is resident and the wait ends; the spin
 // is bounded all the same and a timeout is recorded in *err (reported as an
-// error by the host) instead of waiting forever.
+// error by the host) instead of waiting forever.  The release and acquire are
+// agent-scope even when the work-groups share one XCD: an L1-only invalidate
+// (the workgroup-scope cache operation) left stale blocks visible across
+// compute units and the Jacobi sweeps stopped converging.
 struct LaneBarrier {
   unsigned long long* ctr;
   int* err;
@@ -380,19 +383,17 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
             __syncthreads();
           }
         } else {
-          // cross pairs: column pr of the first block stays in registers.
-          // Only the first nra (A) and nrv (V) row chunks of a thread hold
-          // matrix rows; the chunks past them are zero padding, which no
-          // rotation changes, so they are neither loaded nor rotated.
-          const int nra = (M + TPP - 1) / TPP, nrv = (ncol + TPP - 1) / TPP;
+          // cross pairs: column pr of the first block stays in registers
+          // (all RPT row chunks, the zero padding included: guarding the
+          // padding chunks made the batched chain launch 6 % slower)
           const int c0 = pr;
           zd xr[RPT], xv[RPT];
           const zd* xa = Al + c0 * mpad + lt;
           const zd* xva = Vl + c0 * vpad + lt;
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
-            if (i < nra) xr[i] = xa[i * TPP];
-            if (ACC && i < nrv) xv[i] = xva[i * TPP];
+            xr[i] = xa[i * TPP];
+            if (ACC) xv[i] = xva[i * TPP];
           }
           for (int sub = 0; sub < W; ++sub) {
             const int c1 = W + ((pr + sub) & (W - 1));
@@ -401,14 +402,10 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
             double al0 = 0.0, be0 = 0.0, gr0 = 0.0, gi0 = 0.0, al1 = 0.0, be1 = 0.0, gr1 = 0.0, gi1 = 0.0;
 #pragma unroll
             for (int i = 0; i < RPT; i += 2) {
-              if (i < nra) {
-                yr[i] = y[i * TPP];
-                pair_acc(xr[i], yr[i], al0, be0, gr0, gi0);
-              }
-              if (i + 1 < nra) {
-                yr[i + 1] = y[(i + 1) * TPP];
-                pair_acc(xr[i + 1], yr[i + 1], al1, be1, gr1, gi1);
-              }
+              yr[i] = y[i * TPP];
+              yr[i + 1] = y[(i + 1) * TPP];
+              pair_acc(xr[i], yr[i], al0, be0, gr0, gi0);
+              pair_acc(xr[i + 1], yr[i + 1], al1, be1, gr1, gi1);
             }
             double al = al0 + al1, be = be0 + be1, gr = gr0 + gr1, gi = gi0 + gi1;
             group_sum4<TPP>(al, be, gr, gi);
@@ -417,21 +414,17 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
             if (jacobi_rotation(al, be, gr, gi, tol, floor_g, c, pp, qq)) {
 #pragma unroll
               for (int i = 0; i < RPT; ++i) {
-                if (i < nra) {
-                  const zd u = xr[i], v = yr[i];
-                  xr[i] = rot_x(u, v, c, pp);
-                  y[i * TPP] = rot_y(u, v, c, qq);
-                }
+                const zd u = xr[i], v = yr[i];
+                xr[i] = rot_x(u, v, c, pp);
+                y[i * TPP] = rot_y(u, v, c, qq);
               }
               if (ACC) {
                 zd* yv = Vl + c1 * vpad + lt;
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
-                  if (i < nrv) {
-                    const zd u = xv[i], v = yv[i * TPP];
-                    xv[i] = rot_x(u, v, c, pp);
-                    yv[i * TPP] = rot_y(u, v, c, qq);
-                  }
+                  const zd u = xv[i], v = yv[i * TPP];
+                  xv[i] = rot_x(u, v, c, pp);
+                  yv[i * TPP] = rot_y(u, v, c, qq);
                 }
               }
               rot = true;
@@ -440,8 +433,8 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
           }
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
-            if (i < nra) Al[c0 * mpad + lt + i * TPP] = xr[i];
-            if (ACC && i < nrv) Vl[c0 * vpad + lt + i * TPP] = xv[i];
+            Al[c0 * mpad + lt + i * TPP] = xr[i];
+            if (ACC) Vl[c0 * vpad + lt + i * TPP] = xv[i];
           }
           __syncthreads();
         }
@@ -547,10 +540,15 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
   for (int q = t; q < r; q += 256) s.lam_out[q] = shs[s.perm[q]] / nu;
 }
 
+// stride 8: the grid is 8 P work-groups of which every eighth works, so the
+// P working ones share XCD 0 (work-groups go to the XCDs round-robin) and
+// with it one L2; stride 1: all P work.
 template <int W, bool ACC>
-__global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s) {
-  LaneBarrier bar{s.bar, &s.stats->barrier_timeout, (unsigned long long)gridDim.x, 0ull};
-  svd_body<W, ACC>(s, blockIdx.x, gridDim.x, bar);
+__global__ __launch_bounds__(256) void k_svd_jacobi(SvdArgs s, int stride) {
+  if (blockIdx.x % stride) return;
+  const int nblk = gridDim.x / stride;
+  LaneBarrier bar{s.bar, &s.stats->barrier_timeout, (unsigned long long)nblk, 0ull};
+  svd_body<W, ACC>(s, blockIdx.x / stride, nblk, bar);
 }
 
 // ----------------------------------------------------------------------------
@@ -758,12 +756,9 @@ __device__ void chain_body(const GateLane& ln, const LaneConst& c, int p, int nb
         }
       }
     }
-    // The sweep votes of the lane start at zero.  Other work-groups of the
-    // lane, possibly on other XCDs, update them with device-scope atomics, so
-    // the reset is a device-scope atomic store too: a plain store would sit in
-    // this XCD's L2 and could be ordered differently from the atomics (seen as
-    // work-groups leaving the sweep loop on different sweeps when a lane spans
-    // XCDs).
+    // The sweep votes of the lane start at zero.  The lane's work-groups
+    // update them with device-scope atomics, so the reset is a device-scope
+    // atomic store as well (ordered before the next barrier's release).
     if (p == 0 && threadIdx.x < 128)
       __hip_atomic_store(&ln.rotflag[threadIdx.x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int tile = p; tile < tiles * tiles; tile += nblk)
@@ -1052,8 +1047,13 @@ hipError_t launch_svd(const MpsView& st, int bond, GateWork& w, hipStream_t stre
   const int W = svd_width(st.dcap);
   const int P = (w.ncap + 2 * W - 1) / (2 * W);
   const size_t shm = svd_shared_bytes(st.dcap, w.ldc, w.ldv, mode);
-  void* args[] = {&s};
-  return hipLaunchCooperativeKernel(svd_kernel(W, mode), dim3(P), dim3(256), args, shm, stream);
+  // The P work-groups spread over the XCDs (work-group i on XCD i mod 8).
+  // Packing them onto one XCD (a grid of 8 P with every eighth working) made
+  // saturated 256 x 256 gates slower, 9.3 against 5.5 ms: every barrier's
+  // release and acquire then flush and invalidate the one L2 they all share.
+  int stride = 1;
+  void* args[] = {&s, &stride};
+  return hipLaunchCooperativeKernel(svd_kernel(W, mode), dim3(P * stride), dim3(256), args, shm, stream);
 }
 
 hipError_t launch_update(const MpsView& st, int bond, GateWork& w, hipStream_t stream, GateMode mode) {
