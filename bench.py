@@ -592,6 +592,9 @@ def main():
                     help="parameter vectors per step (0: as many as one launch holds)")
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--ckpt-gates", type=int, default=512)
+    ap.add_argument("--tape-budget-mib", type=int, default=-1,
+                    help="device memory for gate tapes the batched forward pass keeps (-1: what is free after a "
+                         "16 GiB reserve; 0: the last segment only)")
     ap.add_argument("--profile-every", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--budget-s", type=float, default=420.0,
@@ -661,7 +664,8 @@ def main():
 
     ctx.set_progress(progress)
     plan = Plan(ctx, prob.occ, gates, prob.n_qubits, prob.ham_x, prob.ham_z, prob.ham_c, prob.c0,
-                prob.bond_dim, prob.eps, precision=args.precision, ckpt_gates=args.ckpt_gates)
+                prob.bond_dim, prob.eps, precision=args.precision, ckpt_gates=args.ckpt_gates,
+                tape_budget_mib=args.tape_budget_mib)
     nb = args.batch if args.batch > 0 else plan.lanes_per_launch()
     rng = np.random.default_rng(2024)
     thetas = np.stack([prob.theta] + [prob.theta + 0.05 * rng.normal(size=prob.theta.shape) for _ in range(nb - 1)])
@@ -766,7 +770,8 @@ def main():
                    "t_gates_s": stats_single["t_gates_ms"] / 1e3, "t_sweep_s": stats_single["t_sweep_ms"] / 1e3,
                    "t_backward_s": stats_single["t_backward_ms"] / 1e3, "max_bond": stats_single["max_bond"],
                    "discarded_weight_sum": stats_single["discarded_weight_sum"],
-                   "max_jacobi_sweeps": stats_single["max_sweeps_used"], "ckpt_gates": args.ckpt_gates},
+                   "max_jacobi_sweeps": stats_single["max_sweeps_used"], "ckpt_gates": args.ckpt_gates,
+                   "tape_budget_mib": args.tape_budget_mib},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -107,12 +107,19 @@ typedef struct {
  * is saved every ckpt_gates gates and each segment is recomputed in reverse);
  * broaden = eta of the Lorentzian 1/(s_j^2-s_i^2) -> d/(d^2+eta^2) (0 = off);
  * max_sweeps = Jacobi sweep limit; strict_degenerate = 1 makes a degenerate
- * singular pair that carries a cotangent an error (MPS_EDEGEN).            */
+ * singular pair that carries a cotangent an error (MPS_EDEGEN);
+ * tape_budget_mib = device memory (MiB) that mps_energy_grad_batched may hold
+ * for gate tapes recorded by the forward pass, so that the reverse pass
+ * recomputes only the segments that did not fit: 0 = the last segment only,
+ * -1 = as many segments as the free device memory allows after a 16 GiB
+ * reserve, other negative values are MPS_EINVAL.  The tapes stay allocated
+ * with the plan until mps_plan_free.  Results do not depend on it.          */
 typedef struct {
   int32_t ckpt_gates;
   double broaden;
   int32_t max_sweeps;
   int32_t strict_degenerate;
+  int64_t tape_budget_mib;
 } mps_grad_opts;
 
 /* Per-call statistics (any pointer to it may be NULL).                     */

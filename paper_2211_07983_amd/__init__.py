@@ -233,13 +233,13 @@ class Plan:
     """Device copy of (initial state, circuit, Hamiltonian, options): mps_plan."""
 
     def __init__(self, ctx, occ, gates, n_qubits, x, z, coeff, c0, d_max, eps, precision=0,
-                 ckpt_gates=256, broaden=0.0, max_sweeps=64, strict_degenerate=0):
+                 ckpt_gates=256, broaden=0.0, max_sweeps=64, strict_degenerate=0, tape_budget_mib=0):
         self.ctx = ctx
         occ = np.ascontiguousarray(occ, dtype=np.uint8)
         ca = _CircuitArgs(gates)
         pa = _PauliArgs(n_qubits, x, z, coeff, c0)
         tr = Trunc(int(d_max), float(eps), int(precision))
-        go = GradOpts(int(ckpt_gates), float(broaden), int(max_sweeps), int(strict_degenerate))
+        go = GradOpts(int(ckpt_gates), float(broaden), int(max_sweeps), int(strict_degenerate), int(tape_budget_mib))
         h = C.c_void_p()
         ctx.check(ctx._lib.mps_plan_create(ctx.h, _ptr(occ, C.c_uint8), C.byref(ca.c), C.byref(pa.p),
                                            C.byref(tr), C.byref(go), C.byref(h)))

@@ -44,7 +44,8 @@ class PauliSum(C.Structure):
 
 class GradOpts(C.Structure):
     _fields_ = [("ckpt_gates", C.c_int32), ("broaden", C.c_double),
-                ("max_sweeps", C.c_int32), ("strict_degenerate", C.c_int32)]
+                ("max_sweeps", C.c_int32), ("strict_degenerate", C.c_int32),
+                ("tape_budget_mib", C.c_int64)]
 
 
 class Stats(C.Structure):

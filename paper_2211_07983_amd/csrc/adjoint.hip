@@ -1354,7 +1354,28 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
   int* lane_err = (int*)(aux + (size_t)nl * aux_lane);
   unsigned long long* lane_bars = (unsigned long long*)(aux + (size_t)nl * aux_lane + 64);
   HIPCHK(hipMemsetAsync(aux, 0, (size_t)nl * aux_lane + 64 + (size_t)nl * 8, s));
-  char* tape = (char*)B.tape.ensure((size_t)nl * K * L.rec);
+  // Tapes of the last n_keep segments of every lane are recorded by the
+  // forward pass (slot j holds segment n_seg - n_keep + j); the reverse pass
+  // recomputes only the segments before them, into slot 0.
+  const size_t seg_bytes = (size_t)nl * K * L.rec;
+  int n_keep = 1;
+  if (p->opts.tape_budget_mib != 0) {
+    size_t budget = 0;
+    if (p->opts.tape_budget_mib > 0) {
+      budget = (size_t)p->opts.tape_budget_mib << 20;
+    } else {
+      size_t free_b = 0, total_b = 0;
+      HIPCHK(hipMemGetInfo(&free_b, &total_b));
+      const size_t avail = free_b + B.tape.bytes, reserve = (size_t)16 << 30;
+      budget = avail > reserve ? avail - reserve : 0;
+    }
+    n_keep = (int)std::max<size_t>(1, std::min<size_t>((size_t)n_seg, budget / seg_bytes));
+  }
+  char* tape = (char*)B.tape.ensure((size_t)n_keep * seg_bytes);
+  auto tape_of = [&](int sg, int l) {
+    const int j = std::max(0, sg - (n_seg - n_keep));
+    return tape + ((size_t)j * nl + l) * K * L.rec;
+  };
   GateLane* lanes_d = (GateLane*)B.lanes_dev.ensure((size_t)nl * sizeof(GateLane));
   std::vector<GateLane> lh(nl);
   std::vector<AdjWork> W(nl);
@@ -1405,21 +1426,22 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   }
   for (int sg = 0; sg < n_seg; ++sg) {
-    // the last segment records its tape here, so the reverse pass starts
-    // without recomputing it
-    const bool last = sg == n_seg - 1;
+    // the last n_keep segments record their tapes here, so the reverse pass
+    // does not recompute them (earlier segments use slot 0's first record as
+    // their workspace)
+    const bool keep = sg >= n_seg - n_keep;
     for (int l = 0; l < nl; ++l) {
       GateLane& ln = lh[l];
       ln.st = view_of(B.lanes[l]->st);
       ln.g0 = sg * K;
       ln.ng = std::min(G, (sg + 1) * K) - sg * K;
-      ln.rec_stride = last ? 1 : 0;
-      ln.tape = tape + (size_t)l * K * L.rec;
+      ln.rec_stride = keep ? 1 : 0;
+      ln.tape = tape_of(sg, l);
       ln.ckpt = (char*)B.lanes[l]->ckpt.p + (size_t)sg * ckpt_stride;
     }
     HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
     if (prof) HIPCHK(hipEventRecord(ev[0], s));
-    HIPCHK(launch_chain_lanes(lanes_d, nl, lc, last, lane_bars, s));
+    HIPCHK(launch_chain_lanes(lanes_d, nl, lc, keep, lane_bars, s));
     if (prof) HIPCHK(hipEventRecord(ev[1], s));
     // the lane table is rewritten for the next segment only after this one
     // has been consumed
@@ -1461,7 +1483,7 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
   std::vector<GateDims> mx;
   for (int sg = n_seg - 1; sg >= 0; --sg) {
     const int g0 = sg * K, ng = std::min(G, (sg + 1) * K) - g0;
-    const bool taped = sg == n_seg - 1;   // recorded by the forward pass
+    const bool taped = sg >= n_seg - n_keep;   // recorded by the forward pass
     for (int l = 0; l < nl; ++l) {
       BatchLane* bl = B.lanes[l];
       mps_state* rp = bl->rp;
@@ -1476,6 +1498,7 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
       ln.g0 = g0;
       ln.ng = ng;
       ln.rec_stride = 1;
+      ln.tape = tape_of(sg, l);
       ln.ckpt = nullptr;
     }
     HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));

@@ -152,6 +152,7 @@ mps_status mps_plan_create(mps_ctx* ctx, const uint8_t* occ_bits, const mps_circ
       if (p->opts.ckpt_gates <= 0) p->opts.ckpt_gates = 256;
       if (p->opts.max_sweeps <= 0) p->opts.max_sweeps = 64;
       if (!(p->opts.broaden >= 0.0) || !std::isfinite(p->opts.broaden)) fail(MPS_EINVAL, "bad broaden");
+      if (p->opts.tape_budget_mib < -1) fail(MPS_EINVAL, "tape_budget_mib must be >= -1");
       int nth = 0;
       for (int g = 0; g < circuit->n_gates; ++g)
         if (circuit->kind && circuit->kind[g] == 1 && circuit->param) nth = std::max(nth, circuit->param[g] + 1);

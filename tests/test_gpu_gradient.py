@@ -98,6 +98,35 @@ def test_batched_equals_single(ctx, name, nb):
     plan.free()
 
 
+@pytest.mark.parametrize("budget", [-1, 180])
+def test_batched_with_kept_forward_tapes_equals_single(ctx, budget):
+    """The batched form with tapes recorded by the forward pass for several
+    segments (budget -1: every segment fits; 180 MiB: 3 of the 12 segments
+    of 128 gates, the rest recomputed into the first slot) against the
+    single evaluations: the same arithmetic, so the same results."""
+    p, g = configs.load("c1")
+    rng = np.random.default_rng(78)
+    nb = 3
+    thetas = np.stack([p.theta] + [p.theta + 0.05 * rng.normal(size=p.theta.shape) for _ in range(nb - 1)])
+    plan = make_plan(ctx, p, g, ckpt_gates=128, tape_budget_mib=budget)
+    eb, gb, st = plan.energy_grad_batched(thetas)
+    eb2, gb2, _ = plan.energy_grad_batched(thetas)     # buffers reused
+    assert st["n_gates_applied"] == nb * g.n_gates
+    for b in range(nb):
+        e1, g1, _ = plan.energy_grad(thetas[b])
+        assert abs(eb[b] - e1) <= 1e-13 * abs(e1) and abs(eb2[b] - e1) <= 1e-13 * abs(e1)
+        assert np.abs(gb[b] - g1).max() <= 1e-12 * np.abs(g1).max()
+        assert np.abs(gb2[b] - g1).max() <= 1e-12 * np.abs(g1).max()
+    plan.free()
+
+
+def test_negative_tape_budget_is_refused(ctx):
+    from paper_2211_07983_amd import MPSError
+    p, g = configs.load("c1")
+    with pytest.raises(MPSError, match="tape_budget_mib"):
+        make_plan(ctx, p, g, tape_budget_mib=-2)
+
+
 def test_c3_prefix_energy_grad_matches_oracle(ctx):
     """First 2500 gates of the 24-qubit D=128 workload: the middle SVDs are
     256 x 256 and truncate to 128 at every step; E_D and g_D against the oracle."""
