@@ -496,8 +496,18 @@ def mixed_phase(args):
     from vqe_inputs.compile import compile_problem
     from vqe_inputs.problem import make_problem
     from paper_2211_07983_amd import Context, Plan, energy_grad_plans
-    members = [i for i, (n, ne, D, s1, s2) in enumerate(configs.batched_instances()) if n <= args.max_qubits]
+    members = [i for i, (n, ne, D, s1, s2) in enumerate(configs.batched_instances())
+               if n <= args.max_qubits and D <= args.max_d]
     ctx = Context(0)
+    last = [time.perf_counter()]
+
+    def progress(phase, done, total):
+        now = time.perf_counter()
+        if done == total or now - last[0] >= 15.0:
+            log(f"  {phase} {done}/{total}")
+            last[0] = now
+
+    ctx.set_progress(progress)
     probs, plans, circuits = [], [], {}
     for i in members:
         n, ne, D, s1, s2 = configs.batched_instances()[i]
@@ -532,7 +542,7 @@ def mixed_phase(args):
         "ms_per_step": 1e3 * t_mixed, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic (seeded per-instance integrals and theta)",
         "config": {"workload": f"batched-instance set, the {len(plans)} instances with at most {args.max_qubits} "
-                               f"qubits ({len(classes)} (qubits, D) classes), eps={args.eps:g}",
+                               f"qubits and D <= {args.max_d} ({len(classes)} (qubits, D) classes), eps={args.eps:g}",
                    "instances": members, "classes": per_class,
                    "sequential_estimate_s": seq_est,
                    "sequential_note": "one instance per class timed alone, times the class count",
@@ -605,6 +615,7 @@ def main():
     ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr", "vqe", "instances", "mixed", "alg1"],
                     default="evalgrad")
     ap.add_argument("--max-qubits", type=int, default=16, help="--phase mixed: largest instance size taken")
+    ap.add_argument("--max-d", type=int, default=128, help="--phase mixed: largest bond dimension taken")
     ap.add_argument("--class-qubits", type=int, default=12, help="--phase instances: qubit count of the class")
     ap.add_argument("--class-d", type=int, default=64, help="--phase instances: bond dimension of the class")
     ap.add_argument("--vqe-iters", type=int, default=100, help="--phase vqe: iteration limit")

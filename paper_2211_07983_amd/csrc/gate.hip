@@ -251,6 +251,14 @@ struct LaneBarrier {
     // work-group: a single L2 write-back instead of one per wave
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    // A single work-group shares its compute unit's L1 and needs no more:
+    // its blocks go through global memory only to itself, which the
+    // work-group barrier above already orders.  Skipping the agent-scope
+    // fences also spares the other lanes on its XCD an L2 flush per round.
+    if (nblk == 1) {
+      ++gen;
+      return;
+    }
     if (threadIdx.x == 0) {
       const unsigned long long target = (gen + 1) * nblk;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -715,8 +723,11 @@ __device__ inline void copy_words(unsigned long long* dst, const unsigned long l
 // The gate chain of one lane on work-group p of its nblk: ln.ng gates from
 // ln.g0, each contraction tiles, Jacobi SVD and site update with the lane's
 // barrier in between; the state before the first gate goes to ln.ckpt.
+// Always inlined: as a call (the mixed kernel instantiates four widths) it
+// passed its state through the scratch stack, about 1 KB per thread.
 template <int W>
-__device__ void chain_body(const GateLane& ln, const LaneConst& c, int p, int nblk, int record, zd* sbuf) {
+__device__ __attribute__((always_inline)) void chain_body(const GateLane& ln, const LaneConst& c, int p, int nblk,
+                                                          int record, zd* sbuf) {
   LaneBarrier bar{ln.bar, ln.err, (unsigned long long)nblk, 0ull};
   const MpsView& st = ln.st;
   const int dc = st.dcap;

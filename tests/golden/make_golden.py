@@ -45,18 +45,22 @@ def c2_paper():
     return dict(eps=p.eps, E=E, grad=grad.tolist(), bonds=finfo["bonds"])
 
 
-def c3_prefix_grad():
-    """Energy and gradient of the first C3_GRAD_PREFIX gates of C3 at the parity
-    threshold: every middle SVD is full size (256 x 256) and truncates to 128."""
+def c3_prefix_grad(gates=None):
+    """Energy and gradient of the first `gates` (default C3_GRAD_PREFIX) gates
+    of C3 at the parity threshold: every middle SVD is full size (256 x 256)
+    and truncates to 128."""
     import dataclasses
+    n = gates or C3_GRAD_PREFIX
     p, g = configs.load("c3")
-    pre = dataclasses.replace(g, bond=g.bond[:C3_GRAD_PREFIX], kind=g.kind[:C3_GRAD_PREFIX],
-                              pre=g.pre[:C3_GRAD_PREFIX], post=g.post[:C3_GRAD_PREFIX],
-                              param=g.param[:C3_GRAD_PREFIX], coeff=g.coeff[:C3_GRAD_PREFIX])
+    pre = dataclasses.replace(g, bond=g.bond[:n], kind=g.kind[:n], pre=g.pre[:n], post=g.post[:n],
+                              param=g.param[:n], coeff=g.coeff[:n])
     n_theta = int(pre.param.max()) + 1
     E, grad, info = mps.energy_grad(p, pre, p.theta, ckpt=256)
-    return dict(gates=C3_GRAD_PREFIX, n_theta=n_theta, E=E, grad=grad[:n_theta].tolist(),
+    return dict(gates=n, n_theta=n_theta, E=E, grad=grad[:n_theta].tolist(),
                 degenerate_cuts=int(info.get("degenerate_cuts", 0)) if isinstance(info, dict) else 0)
+
+
+C3_GRAD_PREFIX_LONG = 10000   # reaches 97 of the 1818 parameters
 
 
 def c3_prefix():
@@ -175,7 +179,8 @@ ENTRIES = {"c1": lambda: exact_config("c1"), "c2": lambda: exact_config("c2"), "
            "c3_prefix": c3_prefix, "c3_prefix_grad": c3_prefix_grad, "c5_prefix": c5_prefix,
            "c4_3": lambda: batched_instance(3), "c4_4": lambda: batched_instance(4),
            "c5_prefix_grad": c5_prefix_grad, "c2_paper_broaden": c2_paper_broaden,
-           "alg1_c1_groups4": alg1_c1_groups4}
+           "alg1_c1_groups4": alg1_c1_groups4,
+           "c3_prefix_grad_long": lambda: c3_prefix_grad(C3_GRAD_PREFIX_LONG)}
 ENTRIES.update({f"c4p_{i}": (lambda i=i: batched_instance_paper(i)) for i in C4_PARITY})
 # The same instances with the broadened SVD adjoint (eta = C2_BROADEN): where
 # nearly degenerate kept pairs carry cotangents the plain g_D is ill-conditioned
@@ -199,7 +204,7 @@ def rounding_variants(i, broaden):
             p = subprocess.run([sys.executable, os.path.abspath(__file__), "--variant", str(i), repr(broaden), driver],
                                env=env, stdout=subprocess.PIPE, text=True, check=True)
             r = json.loads(p.stdout.strip().splitlines()[-1])
-            out.append(dict(driver=driver, threads=threads, E=r["E"], grad=r["grad"]))
+            out.append(dict(driver=driver, threads=threads, E=r["E"], grad=r["grad"], discarded_sum=r["discarded_sum"]))
     return dict(broaden=broaden, variants=out)
 
 
@@ -223,6 +228,6 @@ def main(names):
 if __name__ == "__main__":
     if sys.argv[1:2] == ["--variant"]:
         r = batched_instance_paper(int(sys.argv[2]), float(sys.argv[3]), sys.argv[4])
-        print(json.dumps(dict(E=r["E"], grad=r["grad"])), flush=True)
+        print(json.dumps(dict(E=r["E"], grad=r["grad"], discarded_sum=r["discarded_sum"])), flush=True)
     else:
         main(sys.argv[1:])

@@ -142,6 +142,25 @@ def test_c3_prefix_energy_grad_matches_oracle(ctx):
     plan.free()
 
 
+def test_c3_long_prefix_energy_grad_matches_oracle(ctx):
+    """First 10000 gates of the 24-qubit D=128 workload (97 of its 1818
+    parameters): E_D and g_D against the oracle, with checkpoints every 256
+    gates, so the reverse pass recomputes 40 segments in three lane batches."""
+    p, g = configs.load("c3")
+    gold = golden()["c3_prefix_grad_long"]
+    pre = Prefix(g, gold["gates"])
+    plan = make_plan(ctx, p, pre, ckpt_gates=256)
+    assert plan.n_theta == gold["n_theta"]
+    e, grad, st = plan.energy_grad(p.theta[:plan.n_theta])
+    ref = np.array(gold["grad"])
+    print(f"c3 long prefix: E error {abs(e - gold['E']):.2e}, grad error "
+          f"{np.abs(grad - ref).max() / max(1.0, np.abs(ref).max()):.2e}, truncated gates {st['gates_truncated']}")
+    assert st["max_bond"] == 128
+    assert rel(e, gold["E"]) <= 1e-10
+    assert grad_ok(grad, ref)
+    plan.free()
+
+
 def test_sweep_limit_is_reported_as_nonconvergence(ctx):
     """With one Jacobi sweep allowed the SVDs cannot converge: MPS_ENOCONV and
     no outputs."""
