@@ -110,19 +110,24 @@ def test_batched_set_instance_matches_oracle(ctx, case):
     if eps > configs.PARITY_EPS:
         assert fst["degenerate_cuts"] == 0
     assert st["max_bond"] == max(gold["bonds"])
-    # each gate's discarded weight is 1 - kept / total in FP64: about 1e-16 of
-    # cancellation per gate on either side
-    assert abs(disc - gold["discarded_sum"]) <= 1e-8 * gold["discarded_sum"] + 1e-15 * len(g.bond)
     if e_tol is None:
         # conditioning-limited: the diameter of the oracle's rounding variants
-        runs = [gref] + golden()[f"c4p_{i}_b_variants"]["variants"]
+        # (energy, gradient and total discarded weight alike)
+        runs = [gold] + golden()[f"c4p_{i}_b_variants"]["variants"]
         gscale = max(1.0, np.abs(ref).max())
         e_spread = max(abs(a["E"] - b["E"]) for a in runs for b in runs)
-        g_spread = max(np.abs(np.array(a["grad"]) - np.array(b["grad"])).max() for a in runs for b in runs) / gscale
-        print(f"  oracle rounding variants: E spread {e_spread:.2e}, grad spread {g_spread:.2e}")
+        d_spread = max(abs(a["discarded_sum"] - b["discarded_sum"]) for a in runs for b in runs)
+        g_runs = [gref] + runs[1:]
+        g_spread = max(np.abs(np.array(a["grad"]) - np.array(b["grad"])).max() for a in g_runs for b in g_runs) / gscale
+        print(f"  oracle rounding variants: E spread {e_spread:.2e}, grad spread {g_spread:.2e}, "
+              f"discarded-weight spread {d_spread:.2e} (GPU {abs(disc - gold['discarded_sum']):.2e})")
+        assert abs(disc - gold["discarded_sum"]) <= SPREAD_FACTOR * d_spread
         assert abs(e - gref["E"]) <= SPREAD_FACTOR * e_spread
         assert gerr <= SPREAD_FACTOR * g_spread
     else:
+        # each gate's discarded weight is 1 - kept / total in FP64: about 1e-16
+        # of cancellation per gate on either side
+        assert abs(disc - gold["discarded_sum"]) <= 1e-8 * gold["discarded_sum"] + 1e-15 * len(g.bond)
         assert rel(e, gold["E"]) <= e_tol
         assert gerr <= g_tol
     if i == 4:
