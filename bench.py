@@ -258,9 +258,10 @@ def cpu_baseline_sample(prob, gates, eps, budget_s=25.0):
 # prefix of the kernel source the counters were taken on: a changed source
 # reports null.
 TRAFFIC = {
-    ("evalgrad", "c2"): {"source": "paper_2211_07983_amd/csrc/gate.hip", "sha": "4788d0911442c081",
-                         "fetch_bytes": 2.58e9, "write_bytes": 116.48e9,
-                         "per": "forward launch of k_chain_lanes<16>, 64 lanes x 512 gates"},
+    ("evalgrad", "c2"): {"source": "paper_2211_07983_amd/csrc/gate.hip", "sha": "f9a17231c8d9f2e9",
+                         "fetch_bytes": 4.446e9, "write_bytes": 116.815e9,
+                         "per": "forward launch of k_chain_lanes<16>, 64 lanes x 512 gates (mean of the 34 launches "
+                                "of a step, 7 of which keep their tapes)"},
     ("sweep", "c3"): {"source": "paper_2211_07983_amd/csrc/sweep32.hip", "sha": "9313886d959f9260",
                       "fetch_bytes": 276.64e9, "write_bytes": 106.78e9,
                       "per": "one sweep (all k_left1_f32 + k_left2_f32 dispatches)"},
