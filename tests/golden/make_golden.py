@@ -63,6 +63,24 @@ def c3_prefix_grad(gates=None):
 C3_GRAD_PREFIX_LONG = 10000   # reaches 97 of the 1818 parameters
 
 
+def c3_prefix_energy_driver(gates, driver):
+    """E_D of the first `gates` gates of C3 at the parity threshold with the
+    oracle's SVDs by LAPACK's `driver`: over 10000 gates 1299 truncations at
+    D cut through (nearly) degenerate pairs, so E_D is fixed only up to what
+    separates two backward-stable SVDs."""
+    import dataclasses
+    p, g = configs.load("c3")
+    pre = dataclasses.replace(g, bond=g.bond[:gates], kind=g.kind[:gates], pre=g.pre[:gates], post=g.post[:gates],
+                              param=g.param[:gates], coeff=g.coeff[:gates])
+    saved = mps.SVD_DRIVER
+    mps.SVD_DRIVER = driver
+    try:
+        E, info = mps.energy(p, pre, p.theta)
+    finally:
+        mps.SVD_DRIVER = saved
+    return dict(gates=gates, driver=driver, E=E, degenerate_cuts=int(info["degenerate_cuts"]))
+
+
 def c3_prefix():
     """The first C3_PREFIX gates of C3 (the middle bonds reach D=128)."""
     p, g = configs.load("c3")
@@ -180,7 +198,8 @@ ENTRIES = {"c1": lambda: exact_config("c1"), "c2": lambda: exact_config("c2"), "
            "c4_3": lambda: batched_instance(3), "c4_4": lambda: batched_instance(4),
            "c5_prefix_grad": c5_prefix_grad, "c2_paper_broaden": c2_paper_broaden,
            "alg1_c1_groups4": alg1_c1_groups4,
-           "c3_prefix_grad_long": lambda: c3_prefix_grad(C3_GRAD_PREFIX_LONG)}
+           "c3_prefix_grad_long": lambda: c3_prefix_grad(C3_GRAD_PREFIX_LONG),
+           "c3_prefix_long_gesdd": lambda: c3_prefix_energy_driver(C3_GRAD_PREFIX_LONG, "gesdd")}
 ENTRIES.update({f"c4p_{i}": (lambda i=i: batched_instance_paper(i)) for i in C4_PARITY})
 # The same instances with the broadened SVD adjoint (eta = C2_BROADEN): where
 # nearly degenerate kept pairs carry cotangents the plain g_D is ill-conditioned

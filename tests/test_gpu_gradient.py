@@ -142,22 +142,31 @@ def test_c3_prefix_energy_grad_matches_oracle(ctx):
     plan.free()
 
 
-def test_c3_long_prefix_energy_grad_matches_oracle(ctx):
+def test_c3_long_prefix_energy_grad_is_valid(ctx):
     """First 10000 gates of the 24-qubit D=128 workload (97 of its 1818
-    parameters): E_D and g_D against the oracle, with checkpoints every 256
-    gates, so the reverse pass recomputes 40 segments in three lane batches."""
+    parameters), checkpoints every 256 gates: 40 segments recomputed in three
+    lane batches.  At the parity threshold 3123 of these gates truncate at D
+    and 1299 of those cuts fall inside (nearly) degenerate pairs, where which
+    of the equal values are kept is arbitrary: E_D is then fixed only up to
+    rounding (the oracle with LAPACK's gesdd instead of gesvd moves it by
+    1.8e-7 Ha) and g_D not at all (the same two oracle runs differ by 42 % of
+    its largest entry).  So the test holds E_D to twice the oracle's driver
+    spread, checks the bonds, the degenerate-cut count and a finite gradient,
+    and leaves g_D unpinned here; the 2500-gate prefix pins it."""
     p, g = configs.load("c3")
     gold = golden()["c3_prefix_grad_long"]
+    alt = golden()["c3_prefix_long_gesdd"]
     pre = Prefix(g, gold["gates"])
     plan = make_plan(ctx, p, pre, ckpt_gates=256)
     assert plan.n_theta == gold["n_theta"]
     e, grad, st = plan.energy_grad(p.theta[:plan.n_theta])
-    ref = np.array(gold["grad"])
-    print(f"c3 long prefix: E error {abs(e - gold['E']):.2e}, grad error "
-          f"{np.abs(grad - ref).max() / max(1.0, np.abs(ref).max()):.2e}, truncated gates {st['gates_truncated']}")
-    assert st["max_bond"] == 128
-    assert rel(e, gold["E"]) <= 1e-10
-    assert grad_ok(grad, ref)
+    spread = abs(alt["E"] - gold["E"])
+    print(f"c3 long prefix: E error {abs(e - gold['E']):.2e} (oracle driver spread {spread:.2e}), "
+          f"degenerate cuts {st['degenerate_cuts']} (oracle {alt['degenerate_cuts']}), "
+          f"truncated gates {st['gates_truncated']}")
+    assert st["max_bond"] == 128 and st["degenerate_cuts"] > 0 and alt["degenerate_cuts"] > 0
+    assert abs(e - gold["E"]) <= 2.0 * spread
+    assert np.all(np.isfinite(grad)) and np.abs(grad).max() > 0.0
     plan.free()
 
 
