@@ -129,20 +129,27 @@ def cpu_baseline_full(prob, gates, eps):
             "seconds_per_eval": dt}
 
 
-def cpu_baseline_settings(workload, eps, timeout_s=150.0):
+def cpu_baseline_settings(workload, eps, deadline):
     """The oracle in the two settings of the timing protocol: BLAS on one thread
-    and on nproc threads, each in a child process whose thread count is fixed
-    by the environment before NumPy loads (changing a loaded BLAS's pool in
-    flight has crashed long oracle runs).  `value`/`cores` are the faster
+    and on nproc threads (the whole evaluation for c1/c2, else the bounded
+    sample), each in a child process whose thread count is fixed by the
+    environment before NumPy loads (changing a loaded BLAS's pool in flight has
+    crashed long oracle runs).  Each child is limited to what is left until
+    `deadline` (time.monotonic), at least 15 s: on these small matrices many
+    BLAS threads are far slower than one, and a setting that does not finish
+    in time is listed with that error.  `value`/`cores` are the faster
     setting's; both are listed under `settings` with the host's core count and
-    CPU model.  A setting that fails is listed with its error."""
+    CPU model."""
     import subprocess
     runs = []
+    mode = "full" if workload in ("c1", "c2") else "sample"
     for n in (1, nproc_threads()):
         if runs and n == runs[0]["requested_threads"]:
             break
         env = dict(os.environ, OPENBLAS_NUM_THREADS=str(n), OMP_NUM_THREADS=str(n), MKL_NUM_THREADS=str(n))
-        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--workload", workload, "--eps", repr(eps)]
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", mode, "--workload", workload,
+               "--eps", repr(eps)]
+        timeout_s = max(15.0, min(150.0, deadline - time.monotonic()))
         try:
             p = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
                                timeout=timeout_s)
@@ -151,30 +158,33 @@ def cpu_baseline_settings(workload, eps, timeout_s=150.0):
             r = json.loads(p.stdout.strip().splitlines()[-1])
         except Exception as exc:   # a failed setting is reported, not fatal to the line
             log(f"cpu baseline with {n} thread(s) failed: {exc}")
-            runs.append({"requested_threads": n, "error": str(exc)[:300]})
+            runs.append({"requested_threads": n, "mode": mode, "error": str(exc)[:300]})
             continue
         r["requested_threads"] = n
-        log(f"cpu baseline, {n} requested / {r['cores']} reported BLAS thread(s): {r['value']:.3e} evals/s "
+        r["mode"] = mode
+        log(f"cpu baseline, {n} requested / {r['cores']} reported BLAS thread(s), {mode}: {r['value']:.3e} evals/s "
             f"({r['seconds_per_eval']:.1f} s/eval); pools {r['thread_pools']}")
         runs.append(r)
     ok = [r for r in runs if "value" in r]
     if not ok:
         return None
     out = dict(max(ok, key=lambda r: r["value"]))
-    out["settings"] = [{k: r[k] for k in ("cores", "requested_threads", "value", "seconds_per_eval", "thread_pools",
-                                          "error") if k in r} for r in runs]
+    out["settings"] = [{k: r[k] for k in ("cores", "requested_threads", "mode", "value", "seconds_per_eval",
+                                          "thread_pools", "error") if k in r} for r in runs]
     out["host"] = host_info()
     return out
 
 
 def cpu_child(args):
-    """--cpu-child: one CPU-baseline setting of the workload (the whole
-    evaluation for c1/c2, a bounded sample otherwise); prints one JSON line.
-    Touches no GPU."""
+    """--cpu-child full|sample: one CPU-baseline setting of the workload (the
+    whole evaluation, or the bounded sample); prints one JSON line.  Touches
+    no GPU."""
     from vqe_inputs import configs
     prob, gates = configs.load(args.workload, eps=args.eps)
-    full = args.workload in ("c1", "c2")
-    r = cpu_baseline_full(prob, gates, prob.eps) if full else cpu_baseline_sample(prob, gates, prob.eps)
+    if args.cpu_child == "full":
+        r = cpu_baseline_full(prob, gates, prob.eps)
+    else:
+        r = cpu_baseline_sample(prob, gates, prob.eps)
     r["thread_pools"] = host_info()["thread_pools"]
     print(json.dumps(r), flush=True)
 
@@ -624,7 +634,7 @@ def main():
                     help="evalgrad phase: 0 plain FP64, 1 Pauli sweeps and sweep adjoint on FP32 matrix cores")
     ap.add_argument("--prefix-gates", type=int, default=3000,
                     help="--phase sweep: gates applied before the sweeps are timed")
-    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-child", choices=["full", "sample"], default=None, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for hardware byte counters)")
@@ -754,7 +764,7 @@ def main():
     ctx.close()
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_settings(args.workload, prob.eps)
+        cpu = cpu_baseline_settings(args.workload, prob.eps, T_START + args.budget_s)
     line = {
         "metric": METRIC,
         "value": value,

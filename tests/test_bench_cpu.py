@@ -44,10 +44,12 @@ def test_cpu_baseline_reports_both_thread_settings_and_the_host():
     fixes, and records the host's core counts and CPU model."""
     sys.path.insert(0, ROOT)
     import bench
-    r = bench.cpu_baseline_settings("c1", 1e-12)
+    import time
+    r = bench.cpu_baseline_settings("c1", 1e-12, time.monotonic() + 300.0)
     assert r["kind"] == "oracle" and r["unit"] == "evals/s" and r["value"] > 0
     assert all("error" not in s for s in r["settings"])
     assert r["settings"][0]["requested_threads"] == 1 and r["settings"][0]["cores"] == 1
+    assert all(s["mode"] == "full" for s in r["settings"])
     assert r["cores"] in [s["cores"] for s in r["settings"]]
     assert r["value"] == max(s["value"] for s in r["settings"])
     host = r["host"]
