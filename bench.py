@@ -564,6 +564,59 @@ def mixed_phase(args):
     print(json.dumps(line), flush=True)
 
 
+def alg1_accuracy_phase(args):
+    """Gradient accuracy under truncation on the GPU path (Sec. 4's comparison
+    of the local gradient with Algorithm 1): the 8-qubit problem at
+    D = 2, 4, 8 against its untruncated gradient (D = 16 holds every Schmidt
+    value of 8 qubits), for the back-propagated fixed-rank gradient g_D, the
+    parameter-shift gradient of the truncated circuit, and Algorithm 1 with
+    four strings per group.  R = |g - g_exact| / |g_exact|."""
+    import numpy as np
+    from vqe_inputs import configs
+    from paper_2211_07983_amd import Context, Plan
+    prob, gates = configs.load("c1")
+    ctx = Context(0)
+
+    def plan_at(D):
+        return Plan(ctx, prob.occ, gates, prob.n_qubits, prob.ham_x, prob.ham_z, prob.ham_c, prob.c0, D, 1e-12)
+
+    exact_plan = plan_at(16)
+    e_ex, g_ex, st = exact_plan.energy_grad(prob.theta)
+    exact_plan.free()
+    if st["gates_truncated"] != 0:
+        raise SystemExit("D = 16 truncated the 8-qubit circuit")
+    nrm = float(np.linalg.norm(g_ex))
+    rows = []
+    for D in (2, 4, 8):
+        pl = plan_at(D)
+        t0 = time.perf_counter()
+        e_d, g_d, sd = pl.energy_grad(prob.theta)
+        _, g_ps, _, _ = pl.energy_grad_psr(prob.theta)
+        row = {"D": D, "E_error": e_d - e_ex, "discarded": sd["discarded_weight_sum"],
+               "R_local": float(np.linalg.norm(g_d - g_ex)) / nrm, "R_psr": float(np.linalg.norm(g_ps - g_ex)) / nrm}
+        for spg in (4,):   # the paper's optimiser runs use four strings per group
+            if spg * D > 128:
+                continue
+            t1 = time.perf_counter()
+            _, g_a, _, _ = pl.energy_grad_alg1(prob.theta, strings_per_group=spg)
+            row[f"R_alg1_{spg}"] = float(np.linalg.norm(g_a - g_ex)) / nrm
+            row[f"t_alg1_{spg}_s"] = time.perf_counter() - t1
+        row["t_s"] = time.perf_counter() - t0
+        log(f"D={D}: " + ", ".join(f"{k} {v:.3g}" for k, v in row.items() if k != "D"))
+        rows.append(row)
+        pl.free()
+    line = {
+        "metric": "relative gradient error R under truncation (GPU path): local g_D, parameter shift, Algorithm 1",
+        "value": rows[0]["R_alg1_4"] if "R_alg1_4" in rows[0] else None, "unit": "R at D=2, Algorithm 1 (4/group)",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c1"] + f", eps=1e-12, {gates.n_gates} NN gates, {prob.n_terms} strings",
+                   "exact": "the same circuit at D = 16 (no truncation)", "E_exact": e_ex, "rows": rows},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def alg1_phase(args):
     """Algorithm 1 (one Pauli string per group, 2 N_h reverse walks) against
     back-propagation on the same plan: 6 qubits (3 orbitals, 2 electrons),
@@ -623,7 +676,8 @@ def main():
                          "not started; the line reports the steps that ran)")
     ap.add_argument("--cpu-reserve-s", type=float, default=90.0,
                     help="share of --budget-s held back for the CPU baseline")
-    ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr", "vqe", "instances", "mixed", "alg1"],
+    ap.add_argument("--phase", choices=["evalgrad", "sweep", "psr", "vqe", "instances", "mixed", "alg1",
+                                        "alg1_accuracy"],
                     default="evalgrad")
     ap.add_argument("--max-qubits", type=int, default=16, help="--phase mixed: largest instance size taken")
     ap.add_argument("--max-d", type=int, default=128, help="--phase mixed: largest bond dimension taken")
@@ -666,6 +720,9 @@ def main():
         return
     if args.phase == "alg1":
         alg1_phase(args)
+        return
+    if args.phase == "alg1_accuracy":
+        alg1_accuracy_phase(args)
         return
     import numpy as np
     from vqe_inputs import configs

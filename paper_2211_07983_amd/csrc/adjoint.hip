@@ -1855,16 +1855,18 @@ void plan_energy_grad_psr(mps_plan* p, const double* theta, int n_theta, double*
 struct MixLaneBufs {
   mps_state* st = nullptr;
   mps_state* rp = nullptr;
-  DevBuf ckpt, Bbar, lambar, gphi, grad, work, tape;
+  std::vector<mps_state*> wrp;   // replay states of a reverse window's segments
+  DevBuf ckpt, Bbar, lambar, gphi, grad, work, tape, wtape;   // wtape: the window's tapes, one per segment
   ~MixLaneBufs() {
     delete st;
     delete rp;
+    for (mps_state* x : wrp) delete x;
   }
 };
 
 struct MixSet {
   std::vector<MixLaneBufs*> lanes;
-  DevBuf thetas, aux, lanes_dev, blk_dev, adj_dev;
+  DevBuf thetas, aux, lanes_dev, blk_dev, adj_dev, raux, rlanes_dev, rblk_dev;
   ~MixSet() {
     for (MixLaneBufs* l : lanes) delete l;
   }
@@ -1923,7 +1925,7 @@ static int mix_block_table(const std::vector<MixInfo>& info, const std::vector<i
 
 static void mixed_group(mps_plan* lead, const std::vector<MixInfo>& info, const std::vector<int>& grp,
                         const std::vector<const double*>& th_dev, double* energies, std::vector<double*>& grad_dev,
-                        GateStats* gsum) {
+                        GateStats* gsum, int cap) {
   mps_ctx* ctx = lead->ctx;
   hipStream_t s = ctx->stream;
   PlanAdj& LA = adj_of(lead);
@@ -2063,115 +2065,192 @@ static void mixed_group(mps_plan* lead, const std::vector<MixInfo>& info, const 
     energies[grp[j]] = ev[0];
     run_sweep_adjoint(p, dims, b->st, (zd*)b->Bbar.p, ev[0], ev[2]);
   }
-  // ---- reverse pass: segment index down; every lane with such a segment
-  // recomputes it (a lane's last one was recorded by the forward pass)
+  // ---- reverse pass in windows of segment indices [bot, top], from the top
+  // down.  In a window every instance recomputes all its segments but its
+  // last (recorded by the forward pass) side by side, one lane per segment,
+  // into the window's tapes; then the gate adjoints of all instances run down
+  // the window, segment index by segment index.  The window is as deep as the
+  // launch's resident work-groups and a tape budget allow.
+  const size_t wtape_budget = (size_t)64 << 30;
+  auto needs = [&](int j, int sg) { return sg < linfo[j].n_seg - 1; };   // recomputed, not recorded
   std::vector<AdjLane> rec;
-  for (int sg = S_max - 1; sg >= 0; --sg) {
-    bool any_recompute = false;
-    for (int j = 0; j < nl; ++j) {
-      const MixInfo& m = linfo[j];
-      MixLane& ml = lh[j];
-      MixLaneBufs* b = S.lanes[j];
-      ml.ln.ckpt = nullptr;
-      if (sg < m.n_seg - 1) {
-        const char* base = (const char*)b->ckpt.p + (size_t)sg * m.ck_stride;
-        HIPCHK(hipMemcpyAsync(b->rp->B.p, base, m.ck_B, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(b->rp->dims.p, base + m.ck_B, m.ck_dims, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(b->rp->lam.p, base + m.ck_lamoff, m.ck_lam, hipMemcpyDeviceToDevice, s));
-        ml.ln.st = view_of(b->rp);
-        ml.ln.g0 = sg * m.K;
-        ml.ln.ng = std::min(m.G, (sg + 1) * m.K) - sg * m.K;
-        ml.ln.rec_stride = 1;
-        ml.record = 1;
-        any_recompute = true;
-      } else {
-        ml.ln.ng = 0;   // no segment, or recorded by the forward pass
-        ml.record = 0;
-      }
+  int top = S_max - 1;
+  while (top >= 0) {
+    // deepest window that fits
+    int depth = 1;
+    for (int d = 2; d <= top + 1; ++d) {
+      std::vector<MixInfo> ri;
+      std::vector<int> idx;
+      size_t tape_bytes = 0;
+      for (int j = 0; j < nl; ++j)
+        for (int sg = top - d + 1; sg <= top; ++sg)
+          if (needs(j, sg)) {
+            idx.push_back((int)ri.size());
+            ri.push_back(linfo[j]);
+            tape_bytes += (size_t)linfo[j].K * linfo[j].L.rec;
+          }
+      std::vector<int2> tb;
+      if ((!ri.empty() && mix_block_table(ri, idx, tb) > cap) || tape_bytes > wtape_budget) break;
+      depth = d;
     }
-    if (any_recompute) launch();
-    // gate sizes of every lane's segment, read back from the tape records
-    std::vector<int> ng(nl, 0), g0(nl, 0);
-    std::vector<std::vector<int>> meta(nl);
-    std::vector<std::vector<double>> dmeta(nl);
-    for (int j = 0; j < nl; ++j) {
-      const MixInfo& m = linfo[j];
-      if (sg >= m.n_seg) continue;
-      g0[j] = sg * m.K;
-      ng[j] = std::min(m.G, (sg + 1) * m.K) - g0[j];
-      meta[j].resize((size_t)ng[j] * 16);
-      dmeta[j].resize((size_t)ng[j] * 16);
-      const char* tb = (const char*)S.lanes[j]->tape.p;
-      HIPCHK(hipMemcpy2DAsync(meta[j].data(), 16 * sizeof(int), tb + m.L.ometa, m.L.rec, 16 * sizeof(int), ng[j],
-                              hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpy2DAsync(dmeta[j].data(), 16 * sizeof(double), tb + m.L.odmeta, m.L.rec, 16 * sizeof(double),
-                              ng[j], hipMemcpyDeviceToHost, s));
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    // lanes in order of decreasing segment length, so that the lanes still
-    // active at step k are a prefix of each step's records
-    std::vector<int> order;
+    const int bot = top - depth + 1;
+    // lanes of the window's recompute: (instance, segment)
+    std::vector<std::pair<int, int>> rl;
     for (int j = 0; j < nl; ++j)
-      if (ng[j] > 0) order.push_back(j);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ng[x] > ng[y]; });
-    if (order.empty()) continue;
-    const int steps = ng[order[0]];
-    rec.clear();
-    std::vector<std::pair<int, GateDims>> step_launch;   // (active lanes, largest sizes)
-    for (int k = 0; k < steps; ++k) {
-      GateDims mx{0, 0, 0, 0, 0, 0.0};
-      int act = 0;
-      for (int j : order) {
-        if (k >= ng[j]) break;
+      for (int sg = bot; sg <= top; ++sg)
+        if (needs(j, sg)) rl.push_back({j, sg});
+    const int nr = (int)rl.size();
+    if (nr > 0) {
+      char* raux = (char*)S.raux.ensure((size_t)nr * aux_lane + 64 + (size_t)nr * 8);
+      int* rerr = (int*)(raux + (size_t)nr * aux_lane);
+      unsigned long long* rbars = (unsigned long long*)(raux + (size_t)nr * aux_lane + 64);
+      HIPCHK(hipMemsetAsync(raux, 0, (size_t)nr * aux_lane + 64 + (size_t)nr * 8, s));
+      std::vector<MixLane> rh(nr);
+      std::vector<MixInfo> ri(nr);
+      std::vector<int> idx(nr);
+      for (int q = 0; q < nr; ++q) {
+        const int j = rl[q].first, sg = rl[q].second, slot = sg - bot;
         const MixInfo& m = linfo[j];
         mps_plan* p = m.p;
         MixLaneBufs* b = S.lanes[j];
-        const int g = g0[j] + ng[j] - 1 - k, q = ng[j] - 1 - k;
-        const int* mt = meta[j].data() + (size_t)q * 16;
-        if (!(mt[0] >= 1 && mt[0] <= m.dc && mt[4] >= 1 && mt[4] <= m.dc && mt[5] >= 1 && mt[5] <= m.dc &&
-              mt[6] >= 1 && mt[6] <= m.dc))
-          fail(MPS_EDEVICE, "gate sizes read back from the tape are out of range");
-        AdjLane a1;
-        a1.R = rec_at((char*)b->tape.p, m.L, q);
-        a1.W = W[j];
-        a1.d = dims_of(mt, dmeta[j].data() + (size_t)q * 16, p->C.bond_h[g]);
-        const int n = a1.d.n;
-        const size_t site = (size_t)m.dc * 2 * m.dc;
-        zd* Bbar = (zd*)b->Bbar.p;
-        double* lambar = (double*)b->lambar.p;
-        a1.Bbn = Bbar + (size_t)n * site;
-        a1.Bbn1 = Bbar + (size_t)(n + 1) * site;
-        a1.lb_out = lambar + (size_t)(n + 1) * m.dc;
-        a1.lb_in = lambar + (size_t)n * m.dc;
-        a1.gphi = (double*)b->gphi.p;
-        a1.theta = th_dev[grp[j]];
-        a1.gt = p->C.tab;
-        a1.g = g;
-        a1.kind = p->C.kind_h[g];
-        a1.dc = m.dc;
-        a1.ldc = m.ldc;
-        a1.ldv = m.ldv;
-        a1.eta = p->opts.broaden;
-        rec.push_back(a1);
-        mx.a = std::max(mx.a, a1.d.a);
-        mx.m = std::max(mx.m, a1.d.m);
-        mx.b = std::max(mx.b, a1.d.b);
-        mx.r = std::max(mx.r, a1.d.r);
-        ++act;
+        while ((int)b->wrp.size() < depth) b->wrp.push_back(plan_new_state(ctx, p->N, p->trunc, nullptr));
+        mps_state* rp = b->wrp[slot];
+        if (rp->N != p->N || rp->dcap != m.dc) {
+          delete rp;
+          rp = b->wrp[slot] = plan_new_state(ctx, p->N, p->trunc, nullptr);
+        }
+        const char* base = (const char*)b->ckpt.p + (size_t)sg * m.ck_stride;
+        HIPCHK(hipMemcpyAsync(rp->B.p, base, m.ck_B, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(rp->dims.p, base + m.ck_B, m.ck_dims, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(rp->lam.p, base + m.ck_lamoff, m.ck_lam, hipMemcpyDeviceToDevice, s));
+        MixLane& ml = rh[q];
+        ml = lh[j];   // the instance's constants, width and work-group count
+        char* la = raux + (size_t)q * aux_lane;
+        ml.ln.rotflag = (int*)la;
+        ml.ln.nrm_part = (double*)(la + 128 * sizeof(int));
+        ml.ln.stats = (GateStats*)(la + 128 * sizeof(int) + 256 * sizeof(double));
+        ml.ln.bar = rbars + q;
+        ml.ln.err = rerr;
+        ml.ln.st = view_of(rp);
+        ml.ln.g0 = sg * m.K;
+        ml.ln.ng = std::min(m.G, (sg + 1) * m.K) - sg * m.K;
+        ml.ln.rec_stride = 1;
+        ml.ln.ckpt = nullptr;
+        ml.record = 1;
+        ri[q] = m;
+        idx[q] = q;
       }
-      step_launch.push_back({act, mx});
+      // each instance's window tapes, as many as its highest slot needs
+      std::vector<int> slots(nl, 0);
+      for (const auto& r : rl) slots[r.first] = std::max(slots[r.first], r.second - bot + 1);
+      for (int j = 0; j < nl; ++j)
+        if (slots[j] > 0) S.lanes[j]->wtape.ensure((size_t)slots[j] * linfo[j].K * linfo[j].L.rec);
+      for (int q = 0; q < nr; ++q) {
+        const int j = rl[q].first, slot = rl[q].second - bot;
+        rh[q].ln.tape = (char*)S.lanes[j]->wtape.p + (size_t)slot * linfo[j].K * linfo[j].L.rec;
+      }
+      std::vector<int2> rblk;
+      const int RT = mix_block_table(ri, idx, rblk);
+      const int2* rblk_d = upload(S.rblk_dev, rblk.data(), rblk.size(), s);
+      MixLane* rlanes_d = (MixLane*)S.rlanes_dev.ensure((size_t)nr * sizeof(MixLane));
+      HIPCHK(hipMemcpyAsync(rlanes_d, rh.data(), (size_t)nr * sizeof(MixLane), hipMemcpyHostToDevice, s));
+      HIPCHK(launch_chain_mixed(rlanes_d, rblk_d, RT, shm, s));
+      HIPCHK(hipStreamSynchronize(s));   // rh and rblk are released at the end of this block
+      int err = 0;
+      HIPCHK(hipMemcpy(&err, rerr, sizeof(int), hipMemcpyDeviceToHost));
+      if (err) fail(MPS_EDEVICE, "a lane barrier of the mixed gate chain timed out");
     }
-    AdjLane* rec_d = (AdjLane*)S.adj_dev.ensure(rec.size() * sizeof(AdjLane));
-    HIPCHK(hipMemcpyAsync(rec_d, rec.data(), rec.size() * sizeof(AdjLane), hipMemcpyHostToDevice, s));
-    size_t off = 0;
-    for (const auto& sl : step_launch) {
-      launch_gate_adjoint(rec_d + off, sl.first, sl.second, gw.stats, s);
-      off += sl.first;
+    // the tape of instance j's segment sg in this window
+    auto tape_of = [&](int j, int sg) -> char* {
+      const MixInfo& m = linfo[j];
+      if (sg == m.n_seg - 1) return (char*)S.lanes[j]->tape.p;
+      return (char*)S.lanes[j]->wtape.p + (size_t)(sg - bot) * m.K * m.L.rec;
+    };
+    for (int sg = top; sg >= bot; --sg) {
+      // gate sizes of every lane's segment, read back from the tape records
+      std::vector<int> ng(nl, 0), g0(nl, 0);
+      std::vector<std::vector<int>> meta(nl);
+      std::vector<std::vector<double>> dmeta(nl);
+      for (int j = 0; j < nl; ++j) {
+        const MixInfo& m = linfo[j];
+        if (sg >= m.n_seg) continue;
+        g0[j] = sg * m.K;
+        ng[j] = std::min(m.G, (sg + 1) * m.K) - g0[j];
+        meta[j].resize((size_t)ng[j] * 16);
+        dmeta[j].resize((size_t)ng[j] * 16);
+        const char* tb = tape_of(j, sg);
+        HIPCHK(hipMemcpy2DAsync(meta[j].data(), 16 * sizeof(int), tb + m.L.ometa, m.L.rec, 16 * sizeof(int), ng[j],
+                                hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpy2DAsync(dmeta[j].data(), 16 * sizeof(double), tb + m.L.odmeta, m.L.rec, 16 * sizeof(double),
+                                ng[j], hipMemcpyDeviceToHost, s));
+      }
+      HIPCHK(hipStreamSynchronize(s));
+      // lanes in order of decreasing segment length, so that the lanes still
+      // active at step k are a prefix of each step's records
+      std::vector<int> order;
+      for (int j = 0; j < nl; ++j)
+        if (ng[j] > 0) order.push_back(j);
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ng[x] > ng[y]; });
+      if (order.empty()) continue;
+      const int steps = ng[order[0]];
+      rec.clear();
+      std::vector<std::pair<int, GateDims>> step_launch;   // (active lanes, largest sizes)
+      for (int k = 0; k < steps; ++k) {
+        GateDims mx{0, 0, 0, 0, 0, 0.0};
+        int act = 0;
+        for (int j : order) {
+          if (k >= ng[j]) break;
+          const MixInfo& m = linfo[j];
+          mps_plan* p = m.p;
+          MixLaneBufs* b = S.lanes[j];
+          const int g = g0[j] + ng[j] - 1 - k, q = ng[j] - 1 - k;
+          const int* mt = meta[j].data() + (size_t)q * 16;
+          if (!(mt[0] >= 1 && mt[0] <= m.dc && mt[4] >= 1 && mt[4] <= m.dc && mt[5] >= 1 && mt[5] <= m.dc &&
+                mt[6] >= 1 && mt[6] <= m.dc))
+            fail(MPS_EDEVICE, "gate sizes read back from the tape are out of range");
+          AdjLane a1;
+          a1.R = rec_at(tape_of(j, sg), m.L, q);
+          a1.W = W[j];
+          a1.d = dims_of(mt, dmeta[j].data() + (size_t)q * 16, p->C.bond_h[g]);
+          const int n = a1.d.n;
+          const size_t site = (size_t)m.dc * 2 * m.dc;
+          zd* Bbar = (zd*)b->Bbar.p;
+          double* lambar = (double*)b->lambar.p;
+          a1.Bbn = Bbar + (size_t)n * site;
+          a1.Bbn1 = Bbar + (size_t)(n + 1) * site;
+          a1.lb_out = lambar + (size_t)(n + 1) * m.dc;
+          a1.lb_in = lambar + (size_t)n * m.dc;
+          a1.gphi = (double*)b->gphi.p;
+          a1.theta = th_dev[grp[j]];
+          a1.gt = p->C.tab;
+          a1.g = g;
+          a1.kind = p->C.kind_h[g];
+          a1.dc = m.dc;
+          a1.ldc = m.ldc;
+          a1.ldv = m.ldv;
+          a1.eta = p->opts.broaden;
+          rec.push_back(a1);
+          mx.a = std::max(mx.a, a1.d.a);
+          mx.m = std::max(mx.m, a1.d.m);
+          mx.b = std::max(mx.b, a1.d.b);
+          mx.r = std::max(mx.r, a1.d.r);
+          ++act;
+        }
+        step_launch.push_back({act, mx});
+      }
+      AdjLane* rec_d = (AdjLane*)S.adj_dev.ensure(rec.size() * sizeof(AdjLane));
+      HIPCHK(hipMemcpyAsync(rec_d, rec.data(), rec.size() * sizeof(AdjLane), hipMemcpyHostToDevice, s));
+      size_t off = 0;
+      for (const auto& sl : step_launch) {
+        launch_gate_adjoint(rec_d + off, sl.first, sl.second, gw.stats, s);
+        off += sl.first;
+      }
+      HIPCHK(hipGetLastError());
+      // rec is rewritten for the next segment index only after this upload
+      HIPCHK(hipStreamSynchronize(s));
+      if (ctx->progress) ctx->progress(ctx->progress_user, "backward", S_max - sg, S_max);
     }
-    HIPCHK(hipGetLastError());
-    // rec is rewritten for the next segment index only after this upload
-    HIPCHK(hipStreamSynchronize(s));
-    if (ctx->progress) ctx->progress(ctx->progress_user, "backward", S_max - sg, S_max);
+    top = bot - 1;
   }
   // ---- chain rule per lane
   for (int j = 0; j < nl; ++j) {
@@ -2252,7 +2331,7 @@ void plan_energy_grad_plans(mps_plan* const* plans, int n, const double* const* 
   std::vector<int> grp;
   auto flush = [&]() {
     if (grp.empty()) return;
-    mixed_group(lead, info, grp, th_dev, energies, g_dev, &gsum);
+    mixed_group(lead, info, grp, th_dev, energies, g_dev, &gsum, cap);
     grp.clear();
   };
   std::vector<int2> blk;
