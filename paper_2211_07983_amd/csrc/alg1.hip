@@ -208,7 +208,7 @@ __device__ inline void block_sum4(double v[4], double (*red)[256]) {
 // Dw = K psi.dcap <= 128.
 __global__ __launch_bounds__(256) void k_compress(MpsView psi, const unsigned long long* xs,
                                                   const unsigned long long* zs, const double* cs, int K, int dmax,
-                                                  double eps, MpsView phi, zd* ws, double* eta) {
+                                                  double eps, MpsView phi, zd* ws, double* eta, GateStats* stats) {
   const int t = threadIdx.x, N = psi.N, dc = psi.dcap, Dw = K * dc;
   __shared__ int wd[65];
   __shared__ double sv[128];
@@ -314,6 +314,7 @@ __global__ __launch_bounds__(256) void k_compress(MpsView psi, const unsigned lo
       for (int e = t; e < a * m2; e += 256) fv[0] += zabs2(Gm[(size_t)(e / m2) * 2 * Dw + e % m2]);
       block_sum4(fv, red);
       const double floor_g = 1e-28 * fv[0];
+      bool converged = false;
       for (int sweep = 0; sweep < 60; ++sweep) {
         if (t == 0) sh_rot = 0;
         __syncthreads();
@@ -354,9 +355,15 @@ __global__ __launch_bounds__(256) void k_compress(MpsView psi, const unsigned lo
             }
             __syncthreads();
           }
-        if (!sh_rot) break;
+        if (!sh_rot) {
+          converged = true;
+          break;
+        }
         __syncthreads();
       }
+      // a compression whose Jacobi sweeps did not converge is reported like a
+      // gate SVD that did not (the host then fails with MPS_ENOCONV)
+      if (!converged && t == 0) atomicAdd(&stats->noconv, 1);
       for (int p = 0; p < a; ++p) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         for (int c = t; c < m2; c += 256) v[0] += zabs2(Gm[(size_t)p * 2 * Dw + c]);
@@ -588,7 +595,16 @@ void plan_energy_grad_alg1(mps_plan* p, const double* theta, int n_theta, int pe
       const int kj = (int)std::min<int64_t>(per_group, K - k0);
       hipLaunchKernelGGL(k_compress, dim3(1), dim3(256), 0, s, vpsiM, (const unsigned long long*)(xsd + k0),
                          (const unsigned long long*)(zsd + k0), (const double*)(csd + k0), kj, p->trunc.d_max,
-                         p->trunc.eps, vphi, cws, etad);
+                         p->trunc.eps, vphi, cws, etad, ctx->gw.stats);
+      // A group whose strings cancel to rounding noise (norm eta below 1e-14
+      // of its weights sum |2 c_k|) contributes nothing; its walk is skipped,
+      // which also keeps an exactly cancelling group (eta = 0, a zero state
+      // whose normalisation has no meaning) out of the gradient.
+      double eta_h = 0.0, wsum = 0.0;
+      for (int k = 0; k < kj; ++k) wsum += std::fabs(c2[k0 + k]);
+      HIPCHK(hipMemcpyAsync(&eta_h, etad, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (!(eta_h > 1e-14 * wsum)) continue;
     } else {
       const double ck = p->H.coeff_h[grp];
       if (ck == 0.0) continue;

@@ -129,3 +129,26 @@ def test_groups_of_four_strings_at_the_compression_bound():
     assert rel(grad, np.array(gold["grad"])) <= 1e-9
     plan.free()
     ctx.close()
+
+
+def test_groups_of_four_strings_from_hartree_fock():
+    """8 qubits at theta = 0 (the Hartree-Fock product state) with four strings
+    per group and D = 16 (no truncation): many groups cancel there to rounding
+    noise (compressed norm eta ~ 1e-16 of their weights), and their walks are
+    skipped.  The gradient is the exact one of the sector simulator, the
+    paper's optimiser start (Sec. 5), where the local gradient is zero."""
+    from oracle import sector as sec
+    from paper_2211_07983_amd import Context, Plan
+    p, g = configs.load("c1")
+    th = np.zeros(p.n_theta)
+    exact = sec.UCCSD(p).gradient(th)
+    ctx = Context(0)
+    plan = Plan(ctx, p.occ, g, p.n_qubits, p.ham_x, p.ham_z, p.ham_c, p.c0, 16, p.eps)
+    _, grad, _, _ = plan.energy_grad_alg1(th, strings_per_group=4)
+    _, g_local, _ = plan.energy_grad(th)
+    print(f"8 q at theta = 0, 4 per group: vs exact {rel(grad, exact):.1e}, |exact| {np.linalg.norm(exact):.3f}")
+    assert np.all(np.isfinite(grad))
+    assert rel(grad, exact) <= 1e-9
+    assert np.abs(g_local).max() <= 1e-12
+    plan.free()
+    ctx.close()
