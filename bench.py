@@ -697,7 +697,7 @@ def main():
         cpu_child(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one MI355X: the hot path runs on a single GPU in this build "
+        print("bench.py measures one MI355X: the hot path runs on a single GPU "
               "(the multi-GPU split is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
