@@ -802,20 +802,24 @@ def main():
     # dominant kernel of the step: the batched gate chain (one cooperative launch
     # per checkpoint segment: contraction, Jacobi SVD and site update of every
     # gate of every vector), each forward launch timed with HIP events on the
-    # context stream; work counted = the SVDs' 84 p^3 (the contractions and
-    # updates it also does are a few percent and not counted)
+    # context stream; work counted = the SVDs' 84 p^3 plus the gate GEMMs the
+    # same launches run (contraction, gate matrix, left update; 8 flops per
+    # complex multiply-add), both reported
     dcap = max(2, ((prob.bond_dim + 1) // 2) * 2)
     W = 32 if dcap <= 32 else 16 if dcap <= 64 else 8 if dcap <= 128 else 4
     src = sb if nb > 1 else st
     n_svd = src["prof_svd_launches"]
     avg_ms = src["prof_svd_ms"] / max(1, n_svd)
-    flop_per_launch = src["prof_svd_flop"] / max(1, n_svd)
+    svd_flop = src["prof_svd_flop"] / max(1, n_svd)
+    gemm_flop = src.get("prof_gemm_flop", 0.0) / max(1, n_svd)
+    flop_per_launch = svd_flop + gemm_flop
     achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12 if n_svd else None
     roofline = {"kernel": f"k_chain_lanes<{W}>" if nb > 1 else f"k_svd_jacobi<{W}, true>", "bound": "alu",
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
                 "traffic": traffic_for("evalgrad", args.workload)[0] if nb == 64 and args.precision == 0 else None,
-                "avg_launch_ms": avg_ms, "flop_per_launch": flop_per_launch, "timed_launches": n_svd}
+                "avg_launch_ms": avg_ms, "flop_per_launch": flop_per_launch, "svd_flop_per_launch": svd_flop,
+                "gemm_flop_per_launch": gemm_flop, "timed_launches": n_svd}
     stats_single = dict(st)
     plan.free()
     ctx.close()

@@ -143,6 +143,10 @@ typedef struct {
   double prof_svd_flop;
   int32_t prof_svd_launches;
   int32_t prof_pad;
+  /* Batched form: the gate GEMM work of the same timed launches (the two-site
+   * contraction, the gate matrix and the left site update, 8 flops per
+   * complex multiply-add; Sec. 3's gate update); 0 for single evaluations.   */
+  double prof_gemm_flop;
 } mps_stats;
 
 /* Context on HIP device `device` using `hip_stream` (a hipStream_t; NULL =

@@ -56,7 +56,8 @@ class Stats(C.Structure):
                 ("t_gates_ms", C.c_double), ("t_sweep_ms", C.c_double),
                 ("t_backward_ms", C.c_double), ("n_gates_applied", C.c_int64),
                 ("prof_svd_ms", C.c_double), ("prof_svd_flop", C.c_double),
-                ("prof_svd_launches", C.c_int32), ("prof_pad", C.c_int32)]
+                ("prof_svd_launches", C.c_int32), ("prof_pad", C.c_int32),
+                ("prof_gemm_flop", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

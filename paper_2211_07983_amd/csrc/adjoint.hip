@@ -1566,6 +1566,7 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
     gsum->disc_sum += x.disc_sum;
     gsum->disc_max = std::max(gsum->disc_max, x.disc_max);
     gsum->svd_flop += x.svd_flop;
+    gsum->gemm_flop += x.gemm_flop;
     gsum->truncated += x.truncated;
     gsum->max_sweeps = std::max(gsum->max_sweeps, x.max_sweeps);
     gsum->noconv += x.noconv;
@@ -1614,6 +1615,7 @@ static void batched_run(mps_plan* p, mps_plan* const* lp, int nb, const double* 
     if (prof_n > 0) {
       stats->prof_svd_ms = prof_ms;
       stats->prof_svd_flop = gsum.svd_flop;
+      stats->prof_gemm_flop = gsum.gemm_flop;
       stats->prof_svd_launches = prof_n;
     }
   }
@@ -2267,6 +2269,7 @@ static void mixed_group(mps_plan* lead, const std::vector<MixInfo>& info, const 
     gsum->disc_sum += x.disc_sum;
     gsum->disc_max = std::max(gsum->disc_max, x.disc_max);
     gsum->svd_flop += x.svd_flop;
+    gsum->gemm_flop += x.gemm_flop;
     gsum->truncated += x.truncated;
     gsum->max_sweeps = std::max(gsum->max_sweeps, x.max_sweeps);
     gsum->noconv += x.noconv;

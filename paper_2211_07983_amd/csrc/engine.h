@@ -23,6 +23,7 @@ struct GateStats {
   double disc_sum;
   double disc_max;
   double svd_flop;   // algorithmic SVD work, 84 p^3 per gate (p = min(rows, cols))
+  double gemm_flop;  // gate GEMM work: 8 flops per complex MAC of the contraction, gate matrix and left update
   int truncated;
   int max_sweeps;
   int noconv;

@@ -540,6 +540,10 @@ __device__ void svd_body(const SvdArgs& s, const int p, const int nblk, Barrier&
     gs->gates += 1;
     const double pp = M < ncol ? M : ncol;
     gs->svd_flop += 84.0 * pp * pp * pp;
+    // the gate's GEMMs around this SVD: (2a x m)(m x 2b) contraction, the 4x4
+    // gate matrix on every (alpha, beta), and the (2a x 2b)(2b x r) update
+    const double ga = a, gb = b, gm = s.dims[n + 1];
+    gs->gemm_flop += 8.0 * (4.0 * ga * gb * gm + 16.0 * ga * gb + 4.0 * ga * gb * r);
     s.dims[n + 1] = r;
   }
   __syncthreads();
