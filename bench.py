@@ -268,8 +268,8 @@ def cpu_baseline_sample(prob, gates, eps, budget_s=25.0):
 # prefix of the kernel source the counters were taken on: a changed source
 # reports null.
 TRAFFIC = {
-    ("evalgrad", "c2"): {"source": "paper_2211_07983_amd/csrc/gate.hip", "sha": "f9a17231c8d9f2e9",
-                         "fetch_bytes": 4.446e9, "write_bytes": 116.815e9,
+    ("evalgrad", "c2"): {"source": "paper_2211_07983_amd/csrc/gate.hip", "sha": "6be98bfd8f61f429",
+                         "fetch_bytes": 4.489e9, "write_bytes": 116.811e9,
                          "per": "forward launch of k_chain_lanes<16>, 64 lanes x 512 gates (mean of the 34 launches "
                                 "of a step, 7 of which keep their tapes)"},
     ("sweep", "c3"): {"source": "paper_2211_07983_amd/csrc/sweep32.hip", "sha": "9313886d959f9260",
