@@ -274,10 +274,12 @@ mps_status mps_energy_grad_multi(mps_plan* const* plans, int32_t n_plans, const 
  * carries its own circuit, capacity, Jacobi block width and work-group
  * count, and a launch advances every lane by one of its own checkpoint
  * segments (lanes whose circuits are shorter finish early).  Energies and
- * sweep adjoints then run per plan, and the reverse pass recomputes the
- * lanes' segments in shared launches and runs the gate adjoints of all lanes
- * step by step in shared launch sets.  Larger sets run in groups that one
- * launch holds.  plans[n_plans]: distinct plans of one context;
+ * sweep adjoints then run per plan.  The reverse pass works through windows
+ * of segment indices from the last down: in a window every plan's segments
+ * are recomputed side by side, one lane per (plan, segment), in one shared
+ * launch, then the gate adjoints of all plans run down the window step by
+ * step in shared launch sets.  Larger sets run in groups that one launch
+ * holds.  plans[n_plans]: distinct plans of one context;
  * thetas[i]: host array of plan i's n_theta parameters; energies: host
  * [n_plans]; grads[i]: host array of plan i's n_theta.  Results equal each
  * plan's mps_energy_grad up to rounding.  stats (nullable): sums and maxima
