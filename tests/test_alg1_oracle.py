@@ -16,14 +16,7 @@ from oracle import alg1, mps
 from oracle import sector as sec
 from oracle import statevector as sv
 from vqe_inputs import configs
-
-
-def dense(m):
-    v = m.B[0].reshape(2, -1)
-    for n in range(1, m.N):
-        a, _, b = m.B[n].shape
-        v = (v @ m.B[n].reshape(a, 2 * b)).reshape(-1, b)
-    return v.reshape(-1)
+from dense_emulation import dense, schmidt_cut
 
 
 @pytest.fixture(scope="module")
@@ -100,20 +93,6 @@ def test_exact_gradient_on_8_qubits():
     assert rel(grad, u.gradient(p.theta)) <= 1e-9
 
 
-def _schmidt_cut(v, n_qubits, cut, D, eps, renorm):
-    """Keeps r = min(D, #{s / |s| > eps}) >= 1 Schmidt components of v across
-    the cut after qubit `cut`; returns (v', smallest gap at the cut)."""
-    M = v.reshape(2 ** (cut + 1), -1)
-    U, s, Vh = np.linalg.svd(M, full_matrices=False)
-    sh = s / np.linalg.norm(s)
-    r = max(1, min(D, int(np.count_nonzero(sh > eps))))
-    gap = (sh[r - 1] - sh[r]) if r < len(s) and sh[r] > 1e-14 else 1.0
-    out = (U[:, :r] * s[:r]) @ Vh[:r]
-    if renorm:
-        out = out / np.linalg.norm(s[:r])
-    return out.reshape(-1), gap
-
-
 def dense_algorithm1(p, g, theta, groups, D, eps):
     """Algorithm 1 on 2^N vectors with the MPS truncations emulated by
     Schmidt truncations; returns (dE/dphi per gate, smallest cut gap)."""
@@ -124,25 +103,25 @@ def dense_algorithm1(p, g, theta, groups, D, eps):
     psi = sv.basis_state(p.occ)
     for k in range(g.n_gates):
         psi = sv.apply_gate(psi, g.matrix(k, theta), int(g.bond[k]), N)
-        psi, gp = _schmidt_cut(psi, N, int(g.bond[k]), D, eps, True)
+        psi, _, gp = schmidt_cut(psi, N, int(g.bond[k]), D, eps, True)
         gap = min(gap, gp)
     ap = sv.PauliApplier(N)
     gphi = np.zeros(g.n_gates)
     for grp in groups:
         phi = sum(2.0 * p.ham_c[k] * ap.apply(psi, p.ham_x[k], p.ham_z[k]) for k in grp)
         for cut in range(N - 2, -1, -1):          # compression: right-to-left sweep
-            phi, gp = _schmidt_cut(phi, N, cut, D, eps, False)
+            phi, _, gp = schmidt_cut(phi, N, cut, D, eps, False)
             gap = min(gap, gp)
         w = psi.copy()
         for k in range(g.n_gates - 1, -1, -1):
             Q = g.matrix(k, theta)
             n = int(g.bond[k])
-            w, gp = _schmidt_cut(sv.apply_gate(w, Q.conj().T, n, N), N, n, D, eps, True)
+            w, _, gp = schmidt_cut(sv.apply_gate(w, Q.conj().T, n, N), N, n, D, eps, True)
             gap = min(gap, gp)
             if g.kind[k] == 1:
                 dQ = g.post[k] @ (-0.5j * zz @ rzz(g.coeff[k] * theta[g.param[k]])) @ g.pre[k]
                 gphi[k] += np.vdot(phi, sv.apply_gate(w, dQ, n, N)).real
-            phi, gp = _schmidt_cut(sv.apply_gate(phi, Q.conj().T, n, N), N, n, D, eps, False)
+            phi, _, gp = schmidt_cut(sv.apply_gate(phi, Q.conj().T, n, N), N, n, D, eps, False)
             gap = min(gap, gp)
     return gphi, gap
 

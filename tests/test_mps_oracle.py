@@ -134,3 +134,42 @@ def test_degenerate_cut_raises_unless_broadened():
     assert np.all(np.isfinite(gb))
     # away from the degeneracy the same circuit has a derivative again
     mps.energy_grad(p, g, p.theta + 0.3)
+
+
+@pytest.mark.parametrize("D,eps", [(2, 1e-12), (4, 1e-12), (64, 1e-2)])
+def test_one_truncating_gate_is_the_schmidt_truncation_at_its_cut(D, eps):
+    """Sec. 3, two-qubit gate update: on a canonical MPS the singular values of
+    lambda_{n-1} C are the state's Schmidt values across the gate's cut, so one
+    truncating gate must leave exactly the state's leading r = min(D,
+    #{s > eps}) Schmidt components, renormalised, with lambda_n their values
+    and the discarded weight the rest.  The reference is a dense SVD of the
+    2^N vector after the gate (the gate matrix from the compiled gate list, not
+    the oracle's).  The state before each checked gate is the untruncated
+    evolution, which stays canonical.  Over a long truncating run the two part:
+    after a cut the left site is no longer exactly canonical, so later
+    truncations are near-optimal, not optimal -- the method's own
+    approximation, which this pin leaves alone.  D = 2, 4 cut by the bond
+    limit; eps = 1e-2 cuts by the threshold."""
+    from dense_emulation import dense, schmidt_cut
+    p, g = configs.small(8, 4, 64, seed=3, theta_sigma=0.3)
+    N = p.n_qubits
+    m = mps.MPS(p.occ)
+    checked = 0
+    for k in range(400):
+        n = int(g.bond[k])
+        after = sv.apply_gate(dense(m), g.matrix(k, p.theta), n, N)
+        _, r_full, _ = schmidt_cut(after, N, n, 10 ** 9, 1e-14, True)
+        ref, r, gap = schmidt_cut(after, N, n, D, eps, True)
+        Q, _ = mps.gate_mats(g, k, p.theta)
+        if r < r_full and gap > 1e-3:
+            t = m.copy()
+            t.apply_gate(n, Q, D, eps)
+            assert t.ranks == [r]
+            assert np.abs(dense(t) - ref).max() <= 1e-12
+            s = np.linalg.svd(after.reshape(2 ** (n + 1), -1), compute_uv=False)
+            assert np.abs(t.lam[n + 1] - s[:r] / np.linalg.norm(s[:r])).max() <= 1e-12
+            assert abs(t.discarded[0] - np.sum(s[r:] ** 2) / np.sum(s ** 2)) <= 1e-13
+            assert t.degenerate_cuts == 0
+            checked += 1
+        m.apply_gate(n, Q, 64, 1e-14)
+    assert checked >= 20
