@@ -75,6 +75,42 @@ def test_random_noncanonical_state_terms_match(ctx):
     assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_random_strings_on_a_random_complex_state(ctx, precision):
+    """Strings of every kind, odd numbers of Y included, on a random complex,
+    non-canonical MPS.  A real Hamiltonian holds only even-Y strings and the
+    UCCSD states are real up to a phase, so on them a conjugated Y phase, a
+    transposed environment or the bra and ket sides swapped in a transfer
+    would go unseen; here the odd-Y values are of order one.  Precision 1 (the
+    FP32 matrix-core transfers) is held to 1e-4 of the normalised values, FP64
+    to 1e-11."""
+    from oracle import mps
+    from paper_2211_07983_amd import State
+    n = 8
+    dims = [1, 2, 4, 6, 8, 6, 4, 2, 1]
+    rng = np.random.default_rng(13)
+    m = mps.MPS([0] * n)
+    for q in range(n):
+        m.B[q] = rng.normal(size=(dims[q], 2, dims[q + 1])) + 1j * rng.normal(size=(dims[q], 2, dims[q + 1]))
+    m.lam = [np.abs(rng.normal(size=d)) + 0.1 for d in dims]
+    xs = rng.integers(0, 2 ** n, 400).astype(np.uint64)
+    zs = rng.integers(0, 2 ** n, 400).astype(np.uint64)
+    coeff = rng.normal(size=400)
+    odd_y = np.array([bin(int(x) & int(z)).count("1") % 2 == 1 for x, z in zip(xs, zs)])
+    e_ref, _, Z, vals = m.energy(xs, zs, coeff, 0.25)
+    assert odd_y.sum() > 50 and np.abs(vals.real[odd_y]).max() > 1e-2
+    st = State.from_tensors(ctx, m.B, m.lam, 8, 1e-12, precision)
+    e, tv, s = st.expect(n, xs, zs, coeff, 0.25, terms=True)
+    st.free()
+    tol = 1e-11 if precision == 0 else 1e-4
+    err = np.abs(tv - vals.real).max()
+    print(f"precision {precision}: max term error {err:.2e} (odd-Y terms {odd_y.sum()}), "
+          f"E error {abs(e - e_ref):.2e}")
+    assert err <= tol
+    assert abs(e - e_ref) <= tol * np.abs(coeff).sum()
+    assert abs(s["norm"] - Z.real) <= (1e-12 if precision == 0 else 1e-5) * abs(Z)
+
+
 def test_import_rejects_bad_arguments(ctx):
     from paper_2211_07983_amd import MPSError, State
     good = [np.ones((1, 2, 2)) / 2, np.ones((2, 2, 1)) / 2]
