@@ -235,3 +235,57 @@ def test_random_strings_on_a_random_complex_mps():
     assert odd_y.sum() > 50 and np.abs(ref.real[odd_y]).max() > 1e-2
     assert np.abs(ref.imag).max() <= 1e-13
     assert np.abs(got - ref).max() <= 1e-12
+
+
+def _random_complex_case():
+    import random_circuit as rc
+    gl, th = rc.circuit(8, 120, 10, 5)
+    return rc.problem(8, 300, 16, 1e-12, 6), gl, th
+
+
+def test_random_complex_circuit_exact_energy_and_gradient():
+    """Beyond the molecular workload: random complex two-qubit gates and a Pauli
+    sum of random strings of every kind, so the state is genuinely complex and
+    odd-Y terms count.  At exact D (16 on 8 qubits) E equals the statevector
+    energy and every gradient entry the Richardson central difference of it."""
+    p, gl, th = _random_complex_case()
+    ap = sv.PauliApplier(8)
+
+    def e_sv(t):
+        return sv.energy(ap, sv.run_gates(gl, p.occ, t), p.ham_x, p.ham_z, p.ham_c, p.c0).real
+
+    E, grad, info = mps.energy_grad(p, gl, th, ckpt=32)
+    assert max(info["discarded"]) < 1e-20
+    assert abs(E - e_sv(th)) <= 1e-12 * max(1.0, abs(E))
+
+    def d(k, h):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        return (e_sv(tp) - e_sv(tm)) / (2 * h)
+    fd = np.array([(4 * d(k, 1e-4) - d(k, 2e-4)) / 3 for k in range(len(th))])
+    assert np.abs(grad - fd).max() <= 1e-8 * np.abs(fd).max()
+
+
+def test_random_complex_circuit_truncating_directional_fd():
+    """The same circuit at D = 4 (41 truncating gates, up to 12 % of the weight
+    discarded, every cut at least 2.7e-2 s_1 from the next value): g_D . v
+    against central differences of E_D with the truncation pattern frozen."""
+    p, gl, th = _random_complex_case()
+    E, grad, info = mps.energy_grad(p, gl, th, D=4)
+    e_info = mps.energy(p, gl, th, D=4)[1]
+    assert max(info["discarded"]) > 0.1 and e_info["degenerate_cuts"] == 0
+    ranks = e_info["ranks"]
+    rng = np.random.default_rng(1)
+    for _ in range(6):
+        v = rng.normal(size=len(th))
+        v /= np.linalg.norm(v)
+
+        def d(h):
+            ep = mps.energy(p, gl, th + h * v, D=4, ranks=ranks)[0]
+            em = mps.energy(p, gl, th - h * v, D=4, ranks=ranks)[0]
+            return (ep - em) / (2 * h)
+        # angles spread over [-pi, pi] and a 12 % truncation curve E_D strongly:
+        # the Richardson error falls as h^4, to ~1e-9 at these steps
+        fd = (4 * d(5e-5) - d(1e-4)) / 3
+        assert abs(fd - grad @ v) <= 1e-7 * max(1.0, np.linalg.norm(grad))
