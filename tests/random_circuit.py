@@ -37,13 +37,13 @@ def circuit(n_qubits, n_gates, n_theta, seed):
     return gl, theta
 
 
-def problem(n_qubits, n_terms, bond_dim, eps, seed):
-    """The fields of a problem that the MPS oracle reads, with a random
-    Pauli sum and a random occupation."""
+def problem(n_qubits, n_terms, bond_dim, eps, seed, n_theta=10):
+    """The fields of a problem that the oracle reads, with a random Pauli sum
+    and a random occupation."""
     rng = np.random.default_rng(seed)
     occ = rng.integers(0, 2, n_qubits).astype(np.uint8)
     x = rng.integers(0, 2 ** n_qubits, n_terms).astype(np.uint64)
     z = rng.integers(0, 2 ** n_qubits, n_terms).astype(np.uint64)
     c = rng.normal(size=n_terms)
     return SimpleNamespace(n_qubits=n_qubits, occ=occ, ham_x=x, ham_z=z, ham_c=c, c0=0.375,
-                           bond_dim=bond_dim, eps=eps)
+                           bond_dim=bond_dim, eps=eps, n_theta=n_theta)

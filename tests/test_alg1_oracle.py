@@ -148,3 +148,28 @@ def test_truncating_regime_is_reported(six, capsys):
     print("Algorithm 1, 6 q, N_h/m = 4: relative gradient error per D " +
           ", ".join(f"D={D}: {r:.2e}" for D, r in out))
     assert out[-1][1] <= 1e-9
+
+
+def test_exact_gradient_on_a_random_complex_circuit():
+    """Random complex gates and random strings of every kind
+    (tests/random_circuit.py): the state is genuinely complex and odd-Y
+    strings count, which the molecular workload never exercises (its strings
+    hold even numbers of Y's, whose phases cancel in pairs).  With four strings
+    per group and no truncation (D = 16 on 8 qubits) the gradient equals the
+    Richardson central differences of the statevector energy."""
+    import random_circuit as rc
+    gl, th = rc.circuit(8, 120, 10, 5)
+    p = rc.problem(8, 300, 16, 1e-12, 6)
+    ap = sv.PauliApplier(8)
+
+    def e_sv(t):
+        return sv.energy(ap, sv.run_gates(gl, p.occ, t), p.ham_x, p.ham_z, p.ham_c, p.c0).real
+
+    def d(k, h):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        return (e_sv(tp) - e_sv(tm)) / (2 * h)
+    fd = np.array([(4 * d(k, 1e-4) - d(k, 2e-4)) / 3 for k in range(len(th))])
+    grad, _ = alg1.energy_grad(p, gl, th, per_group=4)
+    assert rel(grad, fd) <= 1e-9

@@ -59,3 +59,27 @@ def test_random_complex_circuit_matches_oracle(ctx, D, precision):
     assert abs(s["discarded_weight_sum"] - sum(info["discarded"])) <= 1e-10
     assert abs(eb[1] - e) <= 1e-12 * abs(e)
     assert np.abs(gb[1] - g).max() <= 1e-9 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("per_group", [1, 4])
+def test_random_complex_circuit_algorithm_1(ctx, per_group):
+    """The paper's Algorithm 1 (Sec. 4) on the same circuit at exact D: the
+    Pauli images P_k Psi carry odd numbers of Y's here, which the molecular
+    strings never have.  Per-gate dE/dphi against the oracle's Algorithm 1 and
+    the gradient against the oracle's back-propagated one (both exact at this
+    D), to 1e-9 of the largest entry."""
+    from oracle import alg1, mps
+    from paper_2211_07983_amd import Plan
+    p, gl, th = case()
+    _, g_ref, _ = mps.energy_grad(p, gl, th, D=16)
+    _, info = alg1.energy_grad(p, gl, th, per_group=per_group)
+    plan = Plan(ctx, p.occ, gl, 8, p.ham_x, p.ham_z, p.ham_c, p.c0, 16, 1e-12)
+    try:
+        _, g, gphi, _ = plan.energy_grad_alg1(th, strings_per_group=per_group)
+    finally:
+        plan.free()
+    gerr = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    perr = np.abs(gphi - info["gphi"]).max() / np.abs(info["gphi"]).max()
+    print(f"Algorithm 1, {per_group} per group: gradient error {gerr:.2e}, per-gate error {perr:.2e}")
+    assert gerr <= 1e-9
+    assert perr <= 1e-9
