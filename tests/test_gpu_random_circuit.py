@@ -83,3 +83,53 @@ def test_random_complex_circuit_algorithm_1(ctx, per_group):
     print(f"Algorithm 1, {per_group} per group: gradient error {gerr:.2e}, per-gate error {perr:.2e}")
     assert gerr <= 1e-9
     assert perr <= 1e-9
+
+
+def test_random_complex_circuit_parameter_shift(ctx):
+    """Batched parameter shift (Sec. 4, Eq. psr) on the same circuit: every
+    parametric gate's angle c theta_p shifted by +-pi/2, with random
+    coefficients c in {-1, 1/2, 1, 2} carrying the chain rule.  Per-gate
+    dE/dphi and the gradient against the oracle's back-propagated ones at
+    exact D, to 1e-9 of the largest entry."""
+    from oracle import mps
+    from paper_2211_07983_amd import Plan
+    p, gl, th = case()
+    _, g_ref, info = mps.energy_grad(p, gl, th, D=16)
+    plan = Plan(ctx, p.occ, gl, 8, p.ham_x, p.ham_z, p.ham_c, p.c0, 16, 1e-12)
+    try:
+        _, g, gphi, _ = plan.energy_grad_psr(th)
+    finally:
+        plan.free()
+    gerr = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    perr = np.abs(gphi - info["gphi"]).max() / np.abs(info["gphi"]).max()
+    print(f"parameter shift: gradient error {gerr:.2e}, per-gate error {perr:.2e}")
+    assert gerr <= 1e-9 and perr <= 1e-9
+
+
+def test_random_complex_circuits_of_three_sizes_in_shared_launches(ctx):
+    """mps_energy_grad_plans with three random complex circuits of different
+    qubit counts, D and checkpoint intervals: 8 q at exact D = 16, 6 q at
+    D = 4 (10 truncating gates) and 10 q at D = 8 (23 truncating gates), every
+    cut at least 1.7e-2 s_1 from the next value.  Each against the oracle at
+    its own D: E to 1e-10 relative, g to 1e-8 of its largest entry."""
+    import random_circuit as rc
+    from oracle import mps
+    from paper_2211_07983_amd import Plan, energy_grad_plans
+    specs = [(8, 120, 10, 5, 16, 32), (6, 80, 6, 21, 4, 20), (10, 100, 8, 31, 8, 48)]
+    cases, plans = [], []
+    try:
+        for n, G, T, seed, D, ck in specs:
+            gl, th = rc.circuit(n, G, T, seed)
+            p = rc.problem(n, 300 if n == 8 else 150, D, 1e-12, seed + 1, n_theta=T)
+            cases.append((p, gl, th, D))
+            plans.append(Plan(ctx, p.occ, gl, n, p.ham_x, p.ham_z, p.ham_c, p.c0, D, 1e-12, ckpt_gates=ck))
+        es, gs, _ = energy_grad_plans(plans, [c[2] for c in cases])
+    finally:
+        for pl in plans:
+            pl.free()
+    for (p, gl, th, D), e, g in zip(cases, es, gs):
+        e_ref, g_ref, _ = mps.energy_grad(p, gl, th, D=D)
+        gerr = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+        print(f"  {p.n_qubits} q, D={D}: E error {abs(e - e_ref):.2e}, gradient error {gerr:.2e}")
+        assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
+        assert gerr <= 1e-8
