@@ -92,7 +92,9 @@ typedef struct {
 } mps_circuit;
 
 /* H = c0 + sum_k coeff[k] P_k (Sec. 2, Eq. expect-val); x_mask/z_mask are
- * [n_terms][words] with words = ceil(n_qubits/64); coeff is real.           */
+ * [n_terms][words] with words = ceil(n_qubits/64); coeff is real.  The
+ * identity string belongs in c0: a term with x_mask = z_mask = 0, a mask bit
+ * at or beyond n_qubits, or a non-finite coefficient is MPS_EINVAL.        */
 typedef struct {
   int32_t n_qubits;
   int64_t n_terms;

@@ -124,3 +124,23 @@ def test_import_rejects_bad_arguments(ctx):
         State.from_tensors(ctx, bad, lams, 2, 1e-12)
     with pytest.raises(MPSError, match="MPS_EINVAL"):       # negative Schmidt value
         State.from_tensors(ctx, good, [np.ones(1), -np.ones(2), np.ones(1)], 2, 1e-12)
+
+
+def test_pauli_sum_rejects_identity_and_out_of_range_strings(ctx):
+    """The identity string belongs in c0; masks beyond n_qubits and
+    non-finite coefficients are refused before any work."""
+    from paper_2211_07983_amd import MPSError, State
+    st = State.product(ctx, [1, 0, 1, 0], 4, 1e-12)
+    try:
+        e, _, _ = st.expect(4, [0b0011], [0b0001], [0.5], 0.25)
+        assert abs(e - 0.25) <= 1e-15          # Y0 X1 flips two bits of |1010>: <P> = 0
+        with pytest.raises(MPSError, match="MPS_EINVAL"):
+            st.expect(4, [0b0011, 0], [0b0001, 0], [0.5, 1.0], 0.25)
+        with pytest.raises(MPSError, match="MPS_EINVAL"):
+            st.expect(4, [0b10000], [0], [1.0], 0.0)
+        with pytest.raises(MPSError, match="MPS_EINVAL"):
+            st.expect(4, [0b0001], [0], [np.inf], 0.0)
+        e, _, _ = st.expect(4, [0], [0b0101], [2.0], 0.0)
+        assert abs(e - 2.0) <= 1e-15          # Z0 Z2 on |1010>: (-1)(-1) = 1
+    finally:
+        st.free()
