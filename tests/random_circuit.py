@@ -45,5 +45,8 @@ def problem(n_qubits, n_terms, bond_dim, eps, seed, n_theta=10):
     x = rng.integers(0, 2 ** n_qubits, n_terms).astype(np.uint64)
     z = rng.integers(0, 2 ** n_qubits, n_terms).astype(np.uint64)
     c = rng.normal(size=n_terms)
-    return SimpleNamespace(n_qubits=n_qubits, occ=occ, ham_x=x, ham_z=z, ham_c=c, c0=0.375,
+    ident = (x | z) == 0                         # identity strings belong in c0
+    c0 = 0.375 + float(np.sum(c[ident]))
+    keep = ~ident
+    return SimpleNamespace(n_qubits=n_qubits, occ=occ, ham_x=x[keep], ham_z=z[keep], ham_c=c[keep], c0=c0,
                            bond_dim=bond_dim, eps=eps, n_theta=n_theta)

@@ -133,3 +133,30 @@ def test_random_complex_circuits_of_three_sizes_in_shared_launches(ctx):
         print(f"  {p.n_qubits} q, D={D}: E error {abs(e - e_ref):.2e}, gradient error {gerr:.2e}")
         assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
         assert gerr <= 1e-8
+
+
+@pytest.mark.parametrize("n,D", [(2, 2), (2, 1), (3, 2), (3, 1), (5, 4), (5, 2)])
+def test_short_chains(ctx, n, D):
+    """The shortest chains the interface takes (2 qubits: one bond, both
+    sites at the boundary; odd lengths 3 and 5), exact and truncating down to
+    D = 1 (a product state after every gate), random complex circuits with
+    every cut at least 8.9e-2 s_1 from the next value: E to 1e-10 relative and
+    g to 1e-8 of its largest entry against the oracle."""
+    import random_circuit as rc
+    from oracle import mps
+    from paper_2211_07983_amd import Plan
+    G, T, seed = {2: (30, 4, 41), 3: (40, 5, 43), 5: (60, 6, 45)}[n]
+    gl, th = rc.circuit(n, G, T, seed)
+    p = rc.problem(n, 40, D, 1e-12, seed + 1, n_theta=T)
+    e_ref, g_ref, info = mps.energy_grad(p, gl, th, D=D, ckpt=16)
+    plan = Plan(ctx, p.occ, gl, n, p.ham_x, p.ham_z, p.ham_c, p.c0, D, 1e-12, ckpt_gates=16)
+    try:
+        e, g, _ = plan.energy_grad(th)
+        _, s = plan.energy(th)
+    finally:
+        plan.free()
+    gerr = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print(f"{n} q, D={D}: E error {abs(e - e_ref):.2e}, gradient error {gerr:.2e}, max bond {s['max_bond']}")
+    assert s["max_bond"] == max(info["bonds"])
+    assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
+    assert gerr <= 1e-8
