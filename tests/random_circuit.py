@@ -37,13 +37,24 @@ def circuit(n_qubits, n_gates, n_theta, seed):
     return gl, theta
 
 
-def problem(n_qubits, n_terms, bond_dim, eps, seed, n_theta=10):
+def problem(n_qubits, n_terms, bond_dim, eps, seed, n_theta=10, max_weight=None):
     """The fields of a problem that the oracle reads, with a random Pauli sum
-    and a random occupation."""
+    and a random occupation.  max_weight: each string acts on 1..max_weight
+    random qubits (on long chains a dense random string has a vanishing
+    expectation); None: every qubit independently I, X, Y or Z."""
     rng = np.random.default_rng(seed)
     occ = rng.integers(0, 2, n_qubits).astype(np.uint8)
-    x = rng.integers(0, 2 ** n_qubits, n_terms).astype(np.uint64)
-    z = rng.integers(0, 2 ** n_qubits, n_terms).astype(np.uint64)
+    if max_weight is None:
+        x = rng.integers(0, 2 ** n_qubits, n_terms).astype(np.uint64)
+        z = rng.integers(0, 2 ** n_qubits, n_terms).astype(np.uint64)
+    else:
+        x = np.zeros(n_terms, dtype=np.uint64)
+        z = np.zeros(n_terms, dtype=np.uint64)
+        for k in range(n_terms):
+            for q in rng.choice(n_qubits, int(rng.integers(1, max_weight + 1)), replace=False):
+                letter = int(rng.integers(1, 4))           # 1 = X, 2 = Z, 3 = Y
+                x[k] |= np.uint64((letter & 1) << int(q))
+                z[k] |= np.uint64(((letter >> 1) & 1) << int(q))
     c = rng.normal(size=n_terms)
     ident = (x | z) == 0                         # identity strings belong in c0
     c0 = 0.375 + float(np.sum(c[ident]))

@@ -160,3 +160,33 @@ def test_short_chains(ctx, n, D):
     assert s["max_bond"] == max(info["bonds"])
     assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
     assert gerr <= 1e-8
+
+
+def test_sixty_four_qubits(ctx):
+    """The longest chain one mask word holds: 64 qubits, with bit 63 of the
+    masks in use.  A 300-gate random complex circuit at D = 4 (105 truncating
+    gates, every cut at least 3.6e-2 s_1 from the next value), 120 sparse
+    random strings (1 to 4 qubits each) and three strings on the last qubit,
+    one of them spanning the whole chain (Y_0 X_63): E to 1e-10 relative and
+    g to 1e-8 of its largest entry against the oracle."""
+    import random_circuit as rc
+    from oracle import mps
+    from paper_2211_07983_amd import Plan
+    n = 64
+    gl, th = rc.circuit(n, 300, 12, 61)
+    p = rc.problem(n, 120, 4, 1e-12, 62, n_theta=12, max_weight=4)
+    top = np.uint64(1) << np.uint64(63)
+    p.ham_x = np.concatenate([p.ham_x, np.array([0, top | (np.uint64(1) << np.uint64(62)), top | np.uint64(1)],
+                                                dtype=np.uint64)])
+    p.ham_z = np.concatenate([p.ham_z, np.array([top, top, np.uint64(1)], dtype=np.uint64)])
+    p.ham_c = np.concatenate([p.ham_c, [0.7, -0.4, 0.9]])
+    e_ref, g_ref, _ = mps.energy_grad(p, gl, th, D=4, ckpt=64)
+    plan = Plan(ctx, p.occ, gl, n, p.ham_x, p.ham_z, p.ham_c, p.c0, 4, 1e-12, ckpt_gates=64)
+    try:
+        e, g, _ = plan.energy_grad(th)
+    finally:
+        plan.free()
+    gerr = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print(f"64 q, D=4: E error {abs(e - e_ref):.2e}, gradient error {gerr:.2e}")
+    assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
+    assert gerr <= 1e-8
