@@ -190,3 +190,36 @@ def test_sixty_four_qubits(ctx):
     print(f"64 q, D=4: E error {abs(e - e_ref):.2e}, gradient error {gerr:.2e}")
     assert abs(e - e_ref) <= 1e-10 * abs(e_ref)
     assert gerr <= 1e-8
+
+
+def test_batch_spanning_two_lane_groups(ctx):
+    """More parameter vectors than one chain launch holds, so the batch runs
+    as a full lane group and a remainder of two: the 8-qubit circuit at
+    d_max = 64 (four work-groups per lane; the actual bonds stay at or below
+    16), seeded vectors theta + 0.3 N(0, 1).  Vectors on both sides of the
+    group boundary against the oracle (E to 1e-10 relative, g to 1e-8 of its
+    largest entry), and a vector repeated in the second group equal to its
+    first-group result."""
+    from oracle import mps
+    from paper_2211_07983_amd import Plan
+    p, gl, th = case()
+    plan = Plan(ctx, p.occ, gl, 8, p.ham_x, p.ham_z, p.ham_c, p.c0, 64, 1e-12, ckpt_gates=32)
+    try:
+        per = plan.lanes_per_launch()
+        nb = per + 2
+        rng = np.random.default_rng(19)
+        thetas = th + 0.3 * rng.normal(size=(nb, len(th)))
+        thetas[per + 1] = thetas[1]
+        eb, gb, st = plan.energy_grad_batched(thetas)
+    finally:
+        plan.free()
+    print(f"{nb} vectors, {per} per launch")
+    assert st["n_gates_applied"] == nb * gl.n_gates
+    for b in (0, per - 1, per):
+        e_ref, g_ref, _ = mps.energy_grad(p, gl, thetas[b], D=64)
+        gerr = np.abs(gb[b] - g_ref).max() / np.abs(g_ref).max()
+        print(f"  vector {b}: E error {abs(eb[b] - e_ref):.2e}, gradient error {gerr:.2e}")
+        assert abs(eb[b] - e_ref) <= 1e-10 * abs(e_ref)
+        assert gerr <= 1e-8
+    assert abs(eb[per + 1] - eb[1]) <= 1e-13 * abs(eb[1])
+    assert np.abs(gb[per + 1] - gb[1]).max() <= 1e-12 * np.abs(gb[1]).max()
