@@ -1,18 +1,22 @@
 """Energy and gradient beyond the molecular workload (Sec. 3 gate update and
-Pauli sweep, Sec. 4 back-propagation): circuits of random complex two-qubit
-gates and Pauli sums of random strings of every kind, from
-tests/random_circuit.py, through mps_plan_create and mps_energy_grad, against
+Pauli sweep, Sec. 4 back-propagation, Algorithm 1 and the parameter shift):
+circuits of random complex two-qubit gates and Pauli sums of random strings
+of every kind, from tests/random_circuit.py, through the plan calls, against
 the oracle.  The molecular Hamiltonians hold only even-Y strings and the UCCSD
 states are real up to a phase; here neither holds, so a phase or transpose
-slip in the sweep, the sweep adjoint or the gate adjoint would show.
+slip in the sweep, the sweep adjoint, the gate adjoint or the Pauli images of
+Algorithm 1 would show.
 
-Cases (8 qubits, 120 gates, 10 parameters, 300 strings, checkpoints every 32
-gates): exact D = 16 and a truncating D = 4 (41 truncating gates, every cut at
-least 2.7e-2 s_1 from the next value, so the truncation is unique) in FP64,
-E to 1e-10 relative and g to 1e-8 of its largest entry; exact D = 16 in
-precision 1 (FP32 matrix-core sweep transfers), held to the FP32 bound used
-for the molecular cases (term error 4 n 2D 2^-24 times sum |c_k| for E, 1e-5
-of the largest entry for g)."""
+The main case (8 qubits, 120 gates, 10 parameters, 300 strings, checkpoints
+every 32 gates) runs at exact D = 16 and at a truncating D = 4 (41 truncating
+gates, every cut at least 2.7e-2 s_1 from the next value, so the truncation is
+unique) in FP64, E to 1e-10 relative and g to 1e-8 of its largest entry, and
+at exact D = 16 in precision 1 (FP32 matrix-core sweep transfers), held to the
+FP32 bound used for the molecular cases (term error 4 n 2D 2^-24 times
+sum |c_k| for E, 1e-5 of the largest entry for g).  The same circuit then goes
+through Algorithm 1, the batched parameter shift and a batch over two lane
+groups; further cases cover three sizes in one plans-array call, the shortest
+chains (2, 3 and 5 qubits, down to D = 1) and 64 qubits."""
 import numpy as np
 import pytest
 
