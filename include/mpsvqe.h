@@ -199,7 +199,21 @@ mps_status mps_apply_circuit_noalloc(mps_state* st, const mps_circuit* circuit, 
 mps_status mps_expect_paulisum(mps_state* st, const mps_paulisum* h, double* energy,
                                double* term_vals, mps_stats* stats);
 
-/* A reusable device copy of (initial state, circuit, Hamiltonian, options). */
+/* A reusable device copy of (initial state, circuit, Hamiltonian, options)
+ * for mps_plan_energy, mps_energy_grad and the batched, multi-instance,
+ * Algorithm 1 and parameter-shift forms below.  occ_bits: host [n_qubits],
+ * 0 or 1, the starting product state (Sec. 3, Eq. hf); circuit, h and trunc
+ * as described above; opts (nullable): the backward-pass options, with
+ * ckpt_gates <= 0 taken as 256 and max_sweeps <= 0 as 64.  The plan's
+ * parameter count is one more than the largest param[] of a PARAM gate.
+ * Every array is copied to the device during the call.  The gate matrices
+ * are taken to be unitary (the update keeps the right-canonical form only
+ * for unitaries); they are checked for finite entries, not for unitarity.
+ * NULL arguments, n_qubits outside [2, 64], d_max outside [1, 256], a bad
+ * eps, precision or option, a bond, kind or parameter index out of range, a
+ * non-finite entry or a rejected Pauli sum: MPS_EINVAL with nothing
+ * allocated; a failed device allocation: MPS_ENOMEM.  Release the plan with
+ * mps_plan_free.                                                           */
 mps_status mps_plan_create(mps_ctx* ctx, const uint8_t* occ_bits, const mps_circuit* circuit,
                            const mps_paulisum* h, const mps_trunc* trunc,
                            const mps_grad_opts* opts, mps_plan** out);
@@ -339,6 +353,8 @@ mps_status mps_state_import(mps_ctx* ctx, int32_t n_qubits, const mps_trunc* tru
                             const double* B, const double* lam, mps_state** out);
 int32_t mps_state_qubits(const mps_state* st);
 
+/* Release a state or a plan and its device memory, after the work queued on
+ * its context's stream has finished.  NULL is a no-op.                      */
 void mps_state_free(mps_state* st);
 void mps_plan_free(mps_plan* plan);
 
