@@ -224,10 +224,13 @@ mps_status mps_plan_create(mps_ctx* ctx, const uint8_t* occ_bits, const mps_circ
  * theta must stay valid until the call returns.  Errors: n_theta other than
  * the plan's, NULL or non-finite theta: MPS_EINVAL before any work; a Jacobi
  * SVD that does not converge within max_sweeps: MPS_ENOCONV; with
- * strict_degenerate set, a truncation through a degenerate singular pair that
- * carries a cotangent: MPS_EDEGEN (otherwise such pairs are counted in
- * stats->degenerate_cuts); device allocation or runtime failures:
- * MPS_ENOMEM / MPS_EDEVICE.  On error energy and grad are not written.      */
+ * strict_degenerate set, an exactly degenerate singular pair (equal to
+ * 1e-10 relative) that carries a cotangent: MPS_EDEGEN (otherwise that
+ * pair's term of the SVD adjoint is dropped, the d = 0 limit of the
+ * broadened form, and the gradient is returned; the forward truncations
+ * through nearly degenerate pairs are counted in stats->degenerate_cuts);
+ * device allocation or runtime failures: MPS_ENOMEM / MPS_EDEVICE.  On
+ * error energy and grad are not written.                                    */
 mps_status mps_energy_grad(mps_plan* plan, const double* theta, int32_t n_theta,
                            int32_t theta_on_device, double* energy, double* grad,
                            mps_stats* stats);
