@@ -30,8 +30,12 @@
  * copy what they keep (to device memory).  Objects returned through an out
  * pointer belong to the caller and are released with the matching *_free.
  *
- * Errors: every call returns an mps_status; no exception crosses the ABI.  On
- * error the outputs are not written and mps_last_error() describes it.  A
+ * Errors: every call returns an mps_status; no exception crosses the ABI, and
+ * mps_last_error() describes the failure.  Errors found before any work
+ * (MPS_EINVAL) leave the outputs unwritten.  MPS_ENOCONV and MPS_EDEGEN are
+ * found when the work has finished: the outputs then hold what was computed
+ * (with a non-converged SVD, or with the degenerate pair's adjoint term
+ * dropped) and must not be used as results.  A
  * context is bound to one device and one HIP stream; it is not thread safe
  * (use one context per host thread).  Host pointers are plain host memory
  * unless a flag says a pointer is a device address.
@@ -229,8 +233,7 @@ mps_status mps_plan_create(mps_ctx* ctx, const uint8_t* occ_bits, const mps_circ
  * pair's term of the SVD adjoint is dropped, the d = 0 limit of the
  * broadened form, and the gradient is returned; the forward truncations
  * through nearly degenerate pairs are counted in stats->degenerate_cuts);
- * device allocation or runtime failures: MPS_ENOMEM / MPS_EDEVICE.  On
- * error energy and grad are not written.                                    */
+ * device allocation or runtime failures: MPS_ENOMEM / MPS_EDEVICE.        */
 mps_status mps_energy_grad(mps_plan* plan, const double* theta, int32_t n_theta,
                            int32_t theta_on_device, double* energy, double* grad,
                            mps_stats* stats);
