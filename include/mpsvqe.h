@@ -116,10 +116,13 @@ typedef struct {
  * singular pair that carries a cotangent an error (MPS_EDEGEN);
  * tape_budget_mib = device memory (MiB) that mps_energy_grad_batched may hold
  * for gate tapes recorded by the forward pass, so that the reverse pass
- * recomputes only the segments that did not fit: 0 = the last segment only,
- * -1 = as many segments as the free device memory allows after a 16 GiB
- * reserve, other negative values are MPS_EINVAL.  The tapes stay allocated
- * with the plan until mps_plan_free.  Results do not depend on it.          */
+ * recomputes only the segments that did not fit: 0 = the last segment only
+ * (in the full-size tape slot); otherwise the slot plus, in the rest of the
+ * budget, compact copies of the earlier segments' records (only the entries
+ * the gate adjoint reads, at each gate's own bond sizes); -1 = as much as the
+ * free device memory allows after a 16 GiB reserve, other negative values
+ * are MPS_EINVAL.  The tapes stay allocated with the plan until
+ * mps_plan_free.  Results do not depend on it.                              */
 typedef struct {
   int32_t ckpt_gates;
   double broaden;

@@ -1311,10 +1311,111 @@ struct BatchLane {
 struct BatchSet {
   std::vector<BatchLane*> lanes;
   DevBuf thetas, tape, aux, lanes_dev, adj_dev, meta_dev;
+  DevBuf arc, arc_off;   // compact tape records of the forward pass and their offsets
   ~BatchSet() {
     for (BatchLane* l : lanes) delete l;
   }
 };
+
+// Compact copy of one tape record: only the entries the gate adjoint reads,
+// at the gate's own sizes a, m, b (nb = 2b) -- meta, dmeta, perm[0..nb), the
+// singular values sv[perm[i]], lambda_{n-1}[0..a), B_n [a][2][m], B_{n+1}
+// [m][2][b], C (nb columns of 2a rows), the columns perm[i] of A (2a rows
+// each) and the rows perm[i] of V (nb entries each), in that order.
+struct ArcLayout {
+  size_t meta, dmeta, perm, sv, lam, Bl, Br, C, A, V, total;
+};
+
+__host__ __device__ inline size_t al16(size_t x) { return (x + 15) / 16 * 16; }
+
+__host__ __device__ inline ArcLayout arc_layout(int a, int m, int b) {
+  ArcLayout o;
+  const size_t nb = 2 * (size_t)b, z = sizeof(zd);
+  size_t x = 0;
+  o.meta = x;  x = al16(x + 16 * sizeof(int));
+  o.dmeta = x; x = al16(x + 16 * sizeof(double));
+  o.perm = x;  x = al16(x + nb * sizeof(int));
+  o.sv = x;    x = al16(x + nb * sizeof(double));
+  o.lam = x;   x = al16(x + (size_t)a * sizeof(double));
+  o.Bl = x;    x += (size_t)a * 2 * m * z;
+  o.Br = x;    x += (size_t)m * 2 * b * z;
+  o.C = x;     x += 2 * (size_t)a * nb * z;
+  o.A = x;     x += 2 * (size_t)a * nb * z;
+  o.V = x;     x += nb * nb * z;
+  o.total = al16(x);
+  return o;
+}
+
+template <class T>
+__device__ inline void arc_move(T* rec, T* arc, int dir) {
+  if (dir == 0)
+    *arc = *rec;
+  else
+    *rec = *arc;
+}
+
+// dir 0: the records of each lane's current segment (lane tape, one record
+// per step) to the archive; dir 1: back from the archive into the same
+// places of the records.  One block per (step, lane); off[lane * K + step] is
+// the record's byte offset in the archive, -1 = not archived.  The sizes come
+// from the record's meta (dir 0) or the archived meta (dir 1); perm entries
+// outside [0, ncap) are skipped.
+__global__ __launch_bounds__(256) void k_tape_archive(const GateLane* lanes, TapeLayout L, int K, int dc, int ldc,
+                                                      int ldv, int ncap, char* arc, const long long* off, int dir) {
+  const int k = blockIdx.x, l = blockIdx.y, t = threadIdx.x;
+  const GateLane& ln = lanes[l];
+  if (k >= ln.ng) return;
+  const long long o = off[(size_t)l * K + k];
+  if (o < 0) return;
+  char* r = ln.tape + (size_t)k * L.rec;
+  char* q = arc + o;
+  const int* msrc = dir == 0 ? (const int*)(r + L.ometa) : (const int*)q;
+  const int a = msrc[4], m = msrc[5], b = msrc[6], nb = 2 * b;
+  const ArcLayout O = arc_layout(a, m, b);
+  int* rperm = (int*)(r + L.operm);
+  int* qperm = (int*)(q + O.perm);
+  const int* P = dir == 0 ? rperm : qperm;
+  if (t < 16) {
+    arc_move((int*)(r + L.ometa) + t, (int*)(q + O.meta) + t, dir);
+    arc_move((double*)(r + L.odmeta) + t, (double*)(q + O.dmeta) + t, dir);
+  }
+  for (int i = t; i < nb; i += 256) {
+    const int pi = P[i];
+    arc_move(rperm + i, qperm + i, dir);
+    if (pi >= 0 && pi < ncap) arc_move((double*)(r + L.osv) + pi, (double*)(q + O.sv) + i, dir);
+  }
+  for (int i = t; i < a; i += 256) arc_move((double*)(r + L.olam) + i, (double*)(q + O.lam) + i, dir);
+  zd* rBl = (zd*)(r + L.oBl);
+  zd* rBr = (zd*)(r + L.oBr);
+  zd* rC = (zd*)(r + L.oC);
+  zd* rA = (zd*)(r + L.oA);
+  zd* rV = (zd*)(r + L.oV);
+  zd* qBl = (zd*)(q + O.Bl);
+  zd* qBr = (zd*)(q + O.Br);
+  zd* qC = (zd*)(q + O.C);
+  zd* qA = (zd*)(q + O.A);
+  zd* qV = (zd*)(q + O.V);
+  for (int e = t; e < a * 2 * m; e += 256) {
+    const int rowi = e / m, be = e % m;          // rowi = 2 alpha + i
+    arc_move(rBl + (size_t)rowi * dc + be, qBl + e, dir);
+  }
+  for (int e = t; e < m * 2 * b; e += 256) {
+    const int rowj = e / b, be = e % b;          // rowj = 2 gamma + j
+    arc_move(rBr + (size_t)rowj * dc + be, qBr + e, dir);
+  }
+  const int M = 2 * a;
+  for (int e = t; e < nb * M; e += 256) {
+    const int c = e / M, row = e % M;
+    arc_move(rC + (size_t)c * ldc + row, qC + e, dir);
+    const int pc = P[c];
+    if (pc >= 0 && pc < ncap) arc_move(rA + (size_t)pc * ldc + row, qA + e, dir);
+  }
+  for (int e = t; e < nb * nb; e += 256) {
+    const int i = e / nb, c = e % nb;
+    const int pi = P[i];
+    if (pi >= 0 && pi < ncap) arc_move(rV + (size_t)pi * ldv + c, qV + e, dir);
+  }
+}
 
 static BatchSet& batch_of(mps_plan* p) {
   PlanAdj& A = adj_of(p);
@@ -1354,28 +1455,38 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
   int* lane_err = (int*)(aux + (size_t)nl * aux_lane);
   unsigned long long* lane_bars = (unsigned long long*)(aux + (size_t)nl * aux_lane + 64);
   HIPCHK(hipMemsetAsync(aux, 0, (size_t)nl * aux_lane + 64 + (size_t)nl * 8, s));
-  // Tapes of the last n_keep segments of every lane are recorded by the
-  // forward pass (slot j holds segment n_seg - n_keep + j); the reverse pass
-  // recomputes only the segments before them, into slot 0.
+  // One tape slot holds a segment of every lane in the layout that the chain
+  // kernel writes and the gate adjoint reads; the forward pass records the
+  // last segment there, and the reverse pass recomputes the others into it.
+  // With a tape budget every forward segment records its tape, and while the
+  // rest of the budget lasts a compact copy of each record (the entries the
+  // adjoint reads, at the gate's own sizes) goes to the archive; the reverse
+  // pass expands an archived segment back into the slot instead of
+  // recomputing it.
   const size_t seg_bytes = (size_t)nl * K * L.rec;
-  int n_keep = 1;
-  if (p->opts.tape_budget_mib != 0) {
+  char* tape = (char*)B.tape.ensure(seg_bytes);
+  size_t arc_cap = 0;
+  if (p->opts.tape_budget_mib != 0 && n_seg > 1) {
     size_t budget = 0;
     if (p->opts.tape_budget_mib > 0) {
       budget = (size_t)p->opts.tape_budget_mib << 20;
     } else {
       size_t free_b = 0, total_b = 0;
       HIPCHK(hipMemGetInfo(&free_b, &total_b));
-      const size_t avail = free_b + B.tape.bytes, reserve = (size_t)16 << 30;
+      const size_t avail = free_b + B.tape.bytes + B.arc.bytes, reserve = (size_t)16 << 30;
       budget = avail > reserve ? avail - reserve : 0;
     }
-    n_keep = (int)std::max<size_t>(1, std::min<size_t>((size_t)n_seg, budget / seg_bytes));
+    // never more than the earlier segments could need with every bond at capacity
+    const size_t most = (size_t)(n_seg - 1) * nl * K * arc_layout(dc, dc, dc).total;
+    arc_cap = std::min(most, budget > B.tape.bytes ? budget - B.tape.bytes : 0);
   }
-  char* tape = (char*)B.tape.ensure((size_t)n_keep * seg_bytes);
-  auto tape_of = [&](int sg, int l) {
-    const int j = std::max(0, sg - (n_seg - n_keep));
-    return tape + ((size_t)j * nl + l) * K * L.rec;
-  };
+  char* arc = arc_cap > 0 ? (char*)B.arc.ensure(arc_cap) : nullptr;
+  long long* arc_off = arc ? (long long*)B.arc_off.ensure((size_t)n_seg * nl * K * sizeof(long long)) : nullptr;
+  std::vector<char> archived(n_seg, 0);
+  std::vector<long long> off_h(arc ? (size_t)nl * K : 0);
+  size_t arc_used = 0;
+  bool arc_open = arc != nullptr;
+  auto tape_of = [&](int, int l) { return tape + (size_t)l * K * L.rec; };
   GateLane* lanes_d = (GateLane*)B.lanes_dev.ensure((size_t)nl * sizeof(GateLane));
   std::vector<GateLane> lh(nl);
   std::vector<AdjWork> W(nl);
@@ -1425,11 +1536,13 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
     ev.resize(2);
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   }
+  std::vector<int> fmeta(arc ? (size_t)nl * K * 16 : 0);
+  std::vector<double> fdmeta(arc ? (size_t)nl * K * 16 : 0);
   for (int sg = 0; sg < n_seg; ++sg) {
-    // the last n_keep segments record their tapes here, so the reverse pass
-    // does not recompute them (earlier segments use slot 0's first record as
-    // their workspace)
-    const bool keep = sg >= n_seg - n_keep;
+    // the last segment records its tape in the slot, so the reverse pass does
+    // not recompute it (earlier segments use the slot's first record as their
+    // workspace), unless the archive is in use: then every segment records
+    const bool keep = sg == n_seg - 1 || arc_open;
     for (int l = 0; l < nl; ++l) {
       GateLane& ln = lh[l];
       ln.st = view_of(B.lanes[l]->st);
@@ -1451,6 +1564,36 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
       HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
       *prof_ms += t;
       *prof_n += 1;
+    }
+    if (arc_open && sg < n_seg - 1) {
+      // archive the segment if all its records fit what is left (the sizes
+      // are read back and checked first); once one does not, later segments
+      // are recomputed
+      read_lane_meta(lanes_d, lh, nl, L, K, dc, B.meta_dev, fmeta, fdmeta, s);
+      size_t o = arc_used;
+      for (int l = 0; l < nl; ++l)
+        for (int k = 0; k < K; ++k) {
+          long long& x = off_h[(size_t)l * K + k];
+          if (k >= lh[l].ng) {
+            x = -1;
+            continue;
+          }
+          const int* mt = fmeta.data() + ((size_t)l * K + k) * 16;
+          x = (long long)o;
+          o += arc_layout(mt[4], mt[5], mt[6]).total;
+        }
+      if (o > arc_cap) {
+        arc_open = false;
+      } else {
+        long long* od = arc_off + (size_t)sg * nl * K;
+        HIPCHK(hipMemcpyAsync(od, off_h.data(), off_h.size() * sizeof(long long), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_tape_archive, dim3(K, nl), dim3(256), 0, s, (const GateLane*)lanes_d, L, K, dc, gw.ldc,
+                           gw.ldv, gw.ncap, arc, (const long long*)od, 0);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));   // off_h and the lane table are reused
+        archived[sg] = 1;
+        arc_used = o;
+      }
     }
     if (ctx->progress) ctx->progress(ctx->progress_user, "forward", sg + 1, n_seg);
   }
@@ -1483,7 +1626,8 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
   std::vector<GateDims> mx;
   for (int sg = n_seg - 1; sg >= 0; --sg) {
     const int g0 = sg * K, ng = std::min(G, (sg + 1) * K) - g0;
-    const bool taped = sg >= n_seg - n_keep;   // recorded by the forward pass
+    const bool expand = archived[sg] != 0;                 // compact copy in the archive
+    const bool taped = sg == n_seg - 1 || expand;          // no recompute needed
     for (int l = 0; l < nl; ++l) {
       BatchLane* bl = B.lanes[l];
       mps_state* rp = bl->rp;
@@ -1503,6 +1647,11 @@ static void batched_group(mps_plan* p, mps_plan* const* lp, int nl, const double
     }
     HIPCHK(hipMemcpyAsync(lanes_d, lh.data(), (size_t)nl * sizeof(GateLane), hipMemcpyHostToDevice, s));
     if (!taped) HIPCHK(launch_chain_lanes(lanes_d, nl, lc, true, lane_bars, s));
+    if (expand) {
+      hipLaunchKernelGGL(k_tape_archive, dim3(K, nl), dim3(256), 0, s, (const GateLane*)lanes_d, L, K, dc, gw.ldc,
+                         gw.ldv, gw.ncap, arc, (const long long*)(arc_off + (size_t)sg * nl * K), 1);
+      HIPCHK(hipGetLastError());
+    }
     read_lane_meta(lanes_d, lh, nl, L, K, dc, B.meta_dev, meta, dmeta, s);
     int err = 0;
     HIPCHK(hipMemcpyAsync(&err, lane_err, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -98,12 +98,13 @@ def test_batched_equals_single(ctx, name, nb):
     plan.free()
 
 
-@pytest.mark.parametrize("budget", [-1, 180])
+@pytest.mark.parametrize("budget", [-1, 180, 64])
 def test_batched_with_kept_forward_tapes_equals_single(ctx, budget):
-    """The batched form with tapes recorded by the forward pass for several
-    segments (budget -1: every segment fits; 180 MiB: 3 of the 12 segments
-    of 128 gates, the rest recomputed into the first slot) against the
-    single evaluations: the same arithmetic, so the same results."""
+    """The batched form with the forward pass's tapes kept (12 segments of
+    128 gates; the last one stays in the tape slot, the others go to the
+    compact archive while it has room: all eleven at budget -1 and 180 MiB,
+    two at 64 MiB, the rest recomputed) against the single evaluations: the
+    same arithmetic, so the same results, on two calls in a row."""
     p, g = configs.load("c1")
     rng = np.random.default_rng(78)
     nb = 3
