@@ -196,18 +196,21 @@ def test_sixty_four_qubits(ctx):
     assert gerr <= 1e-8
 
 
-def test_batch_spanning_two_lane_groups(ctx):
+@pytest.mark.parametrize("budget", [0, -1])
+def test_batch_spanning_two_lane_groups(ctx, budget):
     """More parameter vectors than one chain launch holds, so the batch runs
     as a full lane group and a remainder of two: the 8-qubit circuit at
     d_max = 64 (four work-groups per lane; the actual bonds stay at or below
-    16), seeded vectors theta + 0.3 N(0, 1).  Vectors on both sides of the
-    group boundary against the oracle (E to 1e-10 relative, g to 1e-8 of its
-    largest entry), and a vector repeated in the second group equal to its
-    first-group result."""
+    16), seeded vectors theta + 0.3 N(0, 1), with the forward tapes recomputed
+    (budget 0) or archived (budget -1, the archive reused by the second
+    group).  Vectors on both sides of the group boundary against the oracle
+    (E to 1e-10 relative, g to 1e-8 of its largest entry), and a vector
+    repeated in the second group equal to its first-group result."""
     from oracle import mps
     from paper_2211_07983_amd import Plan
     p, gl, th = case()
-    plan = Plan(ctx, p.occ, gl, 8, p.ham_x, p.ham_z, p.ham_c, p.c0, 64, 1e-12, ckpt_gates=32)
+    plan = Plan(ctx, p.occ, gl, 8, p.ham_x, p.ham_z, p.ham_c, p.c0, 64, 1e-12, ckpt_gates=32,
+                tape_budget_mib=budget)
     try:
         per = plan.lanes_per_launch()
         nb = per + 2
